@@ -1,0 +1,370 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test is chosen so that a plausible mistake in the oracle (a dropped term,
+a wrong sign or index, a transposed operand, an off-by-one in the sample
+placement or the voxel lookup) fails at least one of them. None of them calls
+the HIP library.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import brute_eq1
+
+BG = (1.0, 1.0, 1.0)
+
+
+def _one_ray_view(eye, target=(0.0, 0.0, 0.0), up=(0.3, 0.2, 1.0)):
+    """A 1x1 image whose only pixel ray is the camera's forward axis."""
+    K = np.array([[1.0, 0, 0.5], [0, 1.0, 0.5], [0, 0, 1]])
+    return K, synth.look_at(eye, target, up=up)
+
+
+def _const_scene(k, D, l, sig, uval, bval, **kw):
+    sigma = np.full((k, k, k), sig, np.float32)
+    u = np.broadcast_to(np.asarray(uval, np.float32).reshape(1, 1, 1, D, 3),
+                        (k, k, k, D, 3)).copy()
+    beta = np.broadcast_to(np.asarray(bval, np.float32).reshape(1, 1, D), (l, l, D)).copy()
+    return oracle.Scene(beta, sigma, u, **kw)
+
+
+def _tiny_random(seed, k=4, D=3, l=4, density=0.6):
+    rng = np.random.default_rng(seed)
+    sigma = (rng.uniform(0, 8, (k, k, k)) * (rng.uniform(size=(k, k, k)) < density)).astype(
+        np.float32)
+    u = rng.uniform(-1, 1, (k, k, k, D, 3)).astype(np.float32)
+    beta = rng.dirichlet(np.ones(D), (l, l)).astype(np.float32)
+    return sigma, u, beta
+
+
+# ----------------------------------------------------------------- Eq. 1 brute force
+
+@pytest.mark.parametrize("seed,in_box,eps", [(0, False, 0.0), (1, True, 0.0), (2, False, 0.3),
+                                             (3, True, 0.05)])
+def test_brute_force_eq1(seed, in_box, eps):
+    """Literal Eq. 1 in 50 digits (O(N^2) transmittance sums, voxel and direction
+    cells found by search) agrees with the oracle to 1e-12 on a tiny scene."""
+    k, D, l, N = 4, 3, 4, 16
+    sigma, u, beta = _tiny_random(seed, k, D, l)
+    sc = oracle.Scene(beta, sigma, u, pos_linear=False, dir_linear=False, in_box=in_box,
+                      bg=(0.2, 0.5, 0.9))
+    v = synth.orbit_view(2.2, 0.3 + seed, 0.35, 3, 3, 1.0, 3.4, f=2.0)
+    res = oracle.render(sc, v.K, v.c2w, 3, 3, v.near, v.far, N, eps, tol=None)
+    for q in range(9):
+        x, y = q % 3, q // 3
+        ref = brute_eq1.render_pixel(sigma, u, beta, k, D, l, v.K, v.c2w, x, y, v.near, v.far,
+                                     N, eps, (0.2, 0.5, 0.9), in_box=in_box)
+        np.testing.assert_allclose(res["rgba"][q], [float(r) for r in ref], rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("eye,target,chord", [
+    ((-4.0, 0.3, -0.2), (0.0, 0.3, -0.2), 2.0),
+    ((-3.0, -3.0, -3.0), (0.0, 0.0, 0.0), 2.0 * math.sqrt(3.0)),
+    ((-3.0, -3.0, 0.1), (0.0, 0.0, 0.1), 2.0 * math.sqrt(2.0))])
+@pytest.mark.parametrize("eps", [0.0, 1e-2])
+def test_homogeneous_medium(eye, target, chord, eps):
+    """Box filled with constant sigma, u and beta, samples inside the box:
+    C = c (1 - exp(-sigma L)) + exp(-sigma L) bg with L the chord length; with
+    termination L becomes n delta, n = min(N, floor(ln(1/eps)/(sigma delta)) + 1)."""
+    D, N, sig = 2, 64, 3.5
+    uval = np.array([[0.3, -0.2, 0.9], [0.5, 0.1, -0.4]], np.float32).astype(np.float64)
+    bval = np.array([0.25, 0.75])
+    c = bval @ uval
+    bg = np.array([0.1, 0.6, 0.35])
+    sc = _const_scene(6, D, 4, sig, uval, bval, in_box=True, bg=tuple(bg))
+    K, c2w = _one_ray_view(eye, target)
+    res = oracle.render(sc, K, c2w, 1, 1, 0.0, 100.0, N, eps, tol=None)
+    L = chord
+    if eps > 0:
+        dl = chord / N
+        n = min(N, math.floor(math.log(1 / eps) / (sig * dl)) + 1)
+        L = n * dl
+    T = math.exp(-sig * L)
+    expect = np.concatenate([c * (1 - T) + T * bg, [1 - T]])
+    np.testing.assert_allclose(res["rgba"][0], expect, rtol=0, atol=1e-12)
+
+
+def test_empty_cache_gives_background():
+    D = 8
+    sc = _const_scene(16, D, 8, 0.0, np.random.default_rng(0).uniform(-1, 1, (D, 3)),
+                      np.full(D, 1.0 / D), bg=(0.3, 0.7, 0.9))
+    v = synth.orbit_view(3.0, 0.7, 0.4, 9, 7, 2.0, 4.0)
+    res = oracle.render(sc, v.K, v.c2w, 7, 9, 2.0, 4.0, 32, 1e-4)
+    assert np.all(res["rgba"] == np.array([0.3, 0.7, 0.9, 0.0]))
+
+
+def test_single_voxel_axis_ray():
+    """One occupied voxel, a ray along +x through the middle of its row:
+    C = c (1 - exp(-sigma n delta)) + exp(-sigma n delta) bg with n the count of
+    sample midpoints inside the voxel's x extent (counted in exact rationals)."""
+    k, D = 8, 1
+    sigma = np.zeros((k, k, k), np.float32)
+    u = np.zeros((k, k, k, D, 3), np.float32)
+    vx, vy, vz = 5, 2, 6
+    sigma[vz, vy, vx] = 7.0
+    u[vz, vy, vx, 0] = [0.9, -0.3, 0.4]
+    beta = np.ones((4, 4, D), np.float32)
+    sc = oracle.Scene(beta, sigma, u, dir_linear=False, bg=BG)
+    h = Fraction(2, k)
+    y0 = -1 + (vy + Fraction(3, 10)) * h
+    z0 = -1 + (vz + Fraction(7, 10)) * h
+    eye = (-3.0, float(y0), float(z0))
+    K, c2w = _one_ray_view(eye, (0.0, float(y0), float(z0)))
+    near, far, N = Fraction(1), Fraction(5), 100
+    res = oracle.render(sc, K, c2w, 1, 1, float(near), float(far), N, 0.0, tol=None)
+    delta = (far - near) / N
+    a, b = -1 + vx * h, -1 + (vx + 1) * h
+    n = sum(1 for i in range(N) if a <= -3 + near + (i + Fraction(1, 2)) * delta < b)
+    assert n == 6
+    T = math.exp(-7.0 * n * float(delta))
+    col = np.array([0.9, -0.3, 0.4], dtype=np.float32).astype(np.float64)
+    expect = np.concatenate([col * (1 - T) + T * np.array(BG), [1 - T]])
+    np.testing.assert_allclose(res["rgba"][0], expect, rtol=0, atol=1e-12)
+
+
+def test_nearest_lookup_matches_cell_search():
+    k, D = 8, 2
+    sigma, u, beta = _tiny_random(5, k, D, 4, density=1.0)
+    sc = oracle.Scene(beta, sigma, u, pos_linear=False)
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(-1.2, 1.2, (500, 3))
+    pts[:20] = rng.integers(0, k + 1, (20, 3)) * (2.0 / k) - 1.0  # exactly on faces
+    sig, uu = oracle.lookup_pos(sc, pts)
+    for p, s, uv in zip(pts, sig, uu):
+        cells = [brute_eq1._cell_of(Fraction(float(x)), Fraction(-1), Fraction(1), k)
+                 for x in p]
+        if any(c is None for c in cells):
+            assert s == 0 and np.all(uv == 0)
+        else:
+            assert s == sigma[cells[2], cells[1], cells[0]]
+            assert np.array_equal(uv, u[cells[2], cells[1], cells[0]])
+
+
+def test_trilinear_reproduces_linear_field():
+    """Values at voxel centres sampled from an affine field are reproduced
+    exactly by the trilinear lookup at interior points."""
+    k, D = 8, 2
+    h = 2.0 / k
+    c = -1 + (np.arange(k) + 0.5) * h
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    sigma = (2.0 + 0.5 * X - 0.25 * Y + 0.75 * Z).astype(np.float32)
+    A = np.random.default_rng(3).uniform(-0.5, 0.5, (D, 3, 4))
+    u = (A[..., 0] * X[..., None, None] + A[..., 1] * Y[..., None, None] +
+         A[..., 2] * Z[..., None, None] + A[..., 3]).astype(np.float32)
+    beta = np.ones((4, 4, D), np.float32)
+    sc = oracle.Scene(beta, sigma, u, pos_linear=True)
+    pts = np.random.default_rng(4).uniform(-1 + h / 2, 1 - h / 2, (300, 3))
+    s, uu = oracle.lookup_pos(sc, pts)
+    xs, ys, zs = pts[:, 0], pts[:, 1], pts[:, 2]
+    np.testing.assert_allclose(s, 2.0 + 0.5 * xs - 0.25 * ys + 0.75 * zs, atol=2e-6)
+    ref = (A[None, ..., 0] * xs[:, None, None] + A[None, ..., 1] * ys[:, None, None]
+           + A[None, ..., 2] * zs[:, None, None] + A[None, ..., 3])
+    np.testing.assert_allclose(uu, ref, atol=2e-6)  # inputs are float32 samples
+
+
+def test_bilinear_direction_lookup():
+    """A field affine in phi at the cell centres is reproduced away from the
+    seam; across the seam the lookup is continuous; a constant field is exact."""
+    l, D = 16, 3
+    ph_c = (np.arange(l) + 0.5) * 2 * math.pi / l
+    coef = np.array([0.2, -0.1, 0.05])
+    beta = np.broadcast_to((0.5 + coef[None, :] * ph_c[:, None])[None], (l, l, D)).astype(
+        np.float32).copy()
+    sc = oracle.Scene(beta, np.zeros((2, 2, 2), np.float32), np.zeros((2, 2, 2, D, 3),
+                                                                         np.float32))
+    rng = np.random.default_rng(7)
+    th = rng.uniform(0.3, 2.8, 200)
+    ph = rng.uniform(ph_c[0], ph_c[-1], 200)
+    dirs = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1)
+    b = oracle.lookup_dir(sc, dirs)
+    np.testing.assert_allclose(b, 0.5 + coef[None, :] * ph[:, None], atol=1e-6)
+    e = 1e-7
+    a1 = oracle.lookup_dir(sc, [[math.cos(-e), math.sin(-e), 0.0]])
+    a2 = oracle.lookup_dir(sc, [[math.cos(e), math.sin(e), 0.0]])
+    np.testing.assert_allclose(a1, a2, atol=1e-6)
+    np.testing.assert_allclose(a1[0], 0.5 + coef * math.pi, atol=1e-6)  # seam = mean of ends
+    const = np.broadcast_to(np.array([0.1, 0.3, 0.6], np.float32), (l, l, D)).copy()
+    sc2 = oracle.Scene(const, np.zeros((2, 2, 2), np.float32),
+                       np.zeros((2, 2, 2, D, 3), np.float32))
+    np.testing.assert_allclose(oracle.lookup_dir(sc2, dirs), np.tile(const[0, 0], (200, 1)),
+                               atol=1e-7)
+
+
+# ----------------------------------------------------------------- rays and intervals
+
+def test_pixel_rays_follow_opencv_axes():
+    W, H, f = 9, 7, 10.8
+    v = synth.orbit_view(3.0, 0.0, 0.0, W, H, 2.0, 4.0, f=f)
+    o, d = oracle.pixel_ray(v.K, v.c2w, H, W, (W - 1) / 2, (H - 1) / 2)
+    np.testing.assert_allclose(o, [3.0, 0.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(d, [-1.0, 0.0, 0.0], atol=1e-15)  # through the look-at point
+    _, dc = oracle.pixel_ray(v.K, v.c2w, H, W, 0, 0)
+    ang = math.atan(math.hypot(W / 2 - 0.5, H / 2 - 0.5) / f)
+    assert abs(math.acos(-dc[0]) - ang) < 1e-12
+    # seen from +x looking at the origin with +z up, image right is world +y
+    assert dc[1] < 0 and dc[2] > 0  # top-left pixel: left and up
+    _, dr = oracle.pixel_ray(v.K, v.c2w, H, W, W - 1, (H - 1) / 2)
+    assert dr[1] > 0 and abs(dr[2]) < 1e-15
+
+
+def test_box_clip_chords():
+    sc = _const_scene(2, 1, 2, 1.0, [[0, 0, 0]], [1.0], in_box=True)
+    hit, t0, t1 = oracle.interval(sc, (-3, 0.2, 0.1), (1, 0, 0), 0.0, 10.0)
+    assert hit and abs(t0 - 2) < 1e-15 and abs(t1 - 4) < 1e-15
+    dd = np.ones(3) / math.sqrt(3)
+    hit, t0, t1 = oracle.interval(sc, -2 * dd * math.sqrt(3), dd, 0.0, 10.0)
+    assert hit and abs((t1 - t0) - 2 * math.sqrt(3)) < 1e-12
+    hit, *_ = oracle.interval(sc, (-3, 1.5, 0.0), (1, 0, 0), 0.0, 10.0)  # parallel, outside
+    assert not hit
+    hit, t0, t1 = oracle.interval(sc, (-3, 0.0, 0.0), (1, 0, 0), 2.5, 3.0)  # near/far inside
+    assert hit and (t0, t1) == (2.5, 3.0)
+
+
+# ----------------------------------------------------------------- compositing
+
+def test_textbook_compositor_d1():
+    """D = 1 and beta = 1 reduce Eq. 5 to c = u; the result equals the classic
+    product-form compositor w_i = alpha_i prod_{j<i} (1 - alpha_j) over the
+    oracle's own samples."""
+    sig, u, beta = synth.scene_arrays(synth.SceneSpec(k=32, D=1, l=4, n_ellipsoids=10,
+                                                      seed=3))[:3]
+    beta[:] = 1.0
+    sc = oracle.Scene(beta, sig, u, bg=(0.25, 0.5, 0.75))
+    v = synth.orbit_view(3.0, 0.4, 0.3, 16, 16, 2.0, 4.0)
+    res = oracle.render(sc, v.K, v.c2w, 16, 16, 2.0, 4.0, 48, 0.0, tol=None)
+    checked = 0
+    for pidx in range(256):
+        x, y = pidx % 16, pidx // 16
+        t, s, rgb, dl = oracle.trace(sc, v.K, v.c2w, 16, 16, 2.0, 4.0, 48, x, y)
+        a = 1.0 - np.exp(-s * dl)
+        w = a * np.concatenate([[1.0], np.cumprod(1.0 - a)[:-1]])
+        C = (w[:, None] * rgb).sum(0) + (1 - w.sum()) * np.array([0.25, 0.5, 0.75])
+        np.testing.assert_allclose(res["rgba"][pidx], np.concatenate([C, [w.sum()]]),
+                                   atol=1e-12)
+        checked += s.max() > 0
+    assert checked >= 30
+
+
+def test_one_hot_beta_selects_component():
+    sig, u, beta = synth.scene_arrays(synth.SceneSpec(k=24, D=4, l=8, n_ellipsoids=3,
+                                                      seed=4))[:3]
+    v = synth.orbit_view(3.0, 1.0, 0.2, 12, 12, 2.0, 4.0)
+    for j in range(4):
+        onehot = np.zeros_like(beta)
+        onehot[..., j] = 1.0
+        a = oracle.render(oracle.Scene(onehot, sig, u), v.K, v.c2w, 12, 12, 2, 4, 40, 1e-3,
+                          tol=None)
+        b = oracle.render(oracle.Scene(np.ones((8, 8, 1), np.float32), sig,
+                                       u[..., j:j + 1, :].copy()), v.K, v.c2w, 12, 12, 2, 4,
+                          40, 1e-3, tol=None)
+        np.testing.assert_array_equal(a["rgba"], b["rgba"])
+
+
+def test_linearity_in_radiance():
+    sig, u, beta = synth.scene_arrays(synth.SceneSpec(k=24, D=3, l=8, n_ellipsoids=4,
+                                                      seed=5))[:3]
+    # radiance on a 2^-10 grid so that the mixture below is exact in float32
+    u = (np.round(u * 1024) / 1024).astype(np.float32)
+    u2 = (np.round(np.random.default_rng(9).uniform(-1, 1, u.shape) * 1024) / 1024).astype(
+        np.float32)
+    v = synth.orbit_view(3.0, 2.0, -0.3, 10, 10, 2.0, 4.0)
+
+    def r(uu):
+        return oracle.render(oracle.Scene(beta, sig, uu, bg=(0, 0, 0)), v.K, v.c2w, 10, 10,
+                             2, 4, 40, 1e-3, tol=None)["rgba"]
+
+    a, b = 0.5, -0.25
+    mix = (np.float64(a) * u + np.float64(b) * u2)
+    assert np.array_equal(mix.astype(np.float32).astype(np.float64), mix)  # exact inputs
+    lhs = r(mix.astype(np.float32))
+    rhs = a * r(u) + b * r(u2)
+    np.testing.assert_allclose(lhs[:, :3], rhs[:, :3], atol=1e-12)
+    np.testing.assert_allclose(lhs[:, 3], r(u)[:, 3], atol=0)
+
+
+def test_weights_and_convexity():
+    sig, u, beta, _ = synth.scene_arrays(synth.SceneSpec(k=32, D=4, l=8, n_ellipsoids=5,
+                                                         seed=6))
+    bg = np.array([0.9, -0.2, 0.4])
+    sc = oracle.Scene(beta, sig, u, bg=tuple(bg))
+    v = synth.orbit_view(3.0, 0.1, 0.5, 14, 14, 2.0, 4.0)
+    res = oracle.render(sc, v.K, v.c2w, 14, 14, 2, 4, 40, 1e-4, tol=None)
+    A = res["rgba"][:, 3]
+    assert np.all((A >= 0) & (A <= 1))
+    for pidx in range(0, 196, 3):
+        _, s, rgb, _ = oracle.trace(sc, v.K, v.c2w, 14, 14, 2, 4, 40, pidx % 14, pidx // 14)
+        used = np.concatenate([rgb[s > 0], bg[None]])
+        lo, hi = used.min(0), used.max(0)
+        c = res["rgba"][pidx, :3]
+        assert np.all(c >= lo - 1e-12) and np.all(c <= hi + 1e-12)
+
+
+def test_termination_error_bound():
+    sig, u, beta, _ = synth.scene_arrays(synth.SceneSpec(k=32, D=4, l=8, n_ellipsoids=6,
+                                                         seed=7))
+    sc = oracle.Scene(beta, sig, u, bg=BG)
+    v = synth.orbit_view(3.0, 0.7, 0.4, 20, 20, 2.0, 4.0)
+    full = oracle.render(sc, v.K, v.c2w, 20, 20, 2, 4, 64, 0.0, tol=None)["rgba"]
+    for eps in (1e-1, 1e-2, 1e-4):
+        cut = oracle.render(sc, v.K, v.c2w, 20, 20, 2, 4, 64, eps, tol=None)["rgba"]
+        # |c| <= 1 (u in [-1,1], beta convex) and bg = 1, so |c - bg| <= 2
+        assert np.abs(cut - full)[:, :3].max() <= 2 * eps + 1e-12
+        assert np.abs(cut - full)[:, 3].max() <= eps + 1e-12
+
+
+def test_segment_split_over_operator():
+    """Compositing [near, mid) and [mid, far) separately and joining them with
+    the over operator equals compositing [near, far)."""
+    sig, u, beta, _ = synth.scene_arrays(synth.SceneSpec(k=32, D=4, l=8, n_ellipsoids=5,
+                                                         seed=8))
+    sc = oracle.Scene(beta, sig, u, bg=(0.0, 0.0, 0.0))
+    v = synth.orbit_view(3.0, 1.3, 0.2, 12, 12, 2.0, 4.0)
+    N, m = 64, 24
+    mid = 2.0 + m * (2.0 / N)
+    full = oracle.render(sc, v.K, v.c2w, 12, 12, 2.0, 4.0, N, 0.0, tol=None)["rgba"]
+    a = oracle.render(sc, v.K, v.c2w, 12, 12, 2.0, mid, m, 0.0, tol=None)["rgba"]
+    b = oracle.render(sc, v.K, v.c2w, 12, 12, mid, 4.0, N - m, 0.0, tol=None)["rgba"]
+    np.testing.assert_allclose(full[:, :3], a[:, :3] + (1 - a[:, 3:]) * b[:, :3], atol=1e-12)
+    np.testing.assert_allclose(1 - full[:, 3], (1 - a[:, 3]) * (1 - b[:, 3]), atol=1e-12)
+
+
+def test_brick_sparse_source_equals_dense():
+    spec = synth.SceneSpec(k=32, D=4, l=8, n_ellipsoids=5, seed=9)
+    sig, u, beta, p = synth.scene_arrays(spec)
+    slot, ss, su = synth.brick_sparse(p, 8)
+    v = synth.orbit_view(3.0, 0.5, 0.3, 16, 16, 2.0, 4.0)
+    dense = oracle.render(oracle.Scene(beta, sig, u, occ_brick=8), v.K, v.c2w, 16, 16, 2, 4,
+                          48, 1e-4)
+    sparse = oracle.render(oracle.Scene(beta, k=32, sparse=(8, slot, ss, su), occ_brick=8),
+                           v.K, v.c2w, 16, 16, 2, 4, 48, 1e-4)
+    assert np.array_equal(dense["rgba"], sparse["rgba"])
+    assert dense["counts"] == sparse["counts"]
+    assert dense["counts"]["occ_samples"] >= dense["counts"]["nonzero_samples"] > 0
+
+
+def test_ambiguous_face_gives_both_candidates():
+    """A ray whose samples land exactly on a voxel face admits both voxels."""
+    k, D = 4, 1
+    sigma = np.zeros((k, k, k), np.float32)
+    u = np.zeros((k, k, k, D, 3), np.float32)
+    sigma[1, 1, 1] = 5.0
+    sigma[1, 1, 2] = 9.0
+    u[1, 1, 1, 0] = [1, 0, 0]
+    u[1, 1, 2, 0] = [0, 1, 0]
+    beta = np.ones((3, 3, 1), np.float32)  # l = 3: the ray is not on a direction-cell border
+    sc = oracle.Scene(beta, sigma, u, dir_linear=False, bg=(0, 0, 0))
+    # a ray along +y at x exactly on the face between voxels 1 and 2 (x = 0)
+    K, c2w = _one_ray_view((0.0, -3.0, -0.25), (0.0, 0.0, -0.25), up=(0.0, 0.0, 1.0))
+    res = oracle.render(sc, K, c2w, 1, 1, 2.0, 4.0, 8, 0.0)
+    # two samples lie in the voxel row y = 1, z = 1, each on the x face
+    assert res["ncand"][0] == 4 and res["flags"][0] & oracle.AMBIG
+    first, last = res["cand"][0, 0], res["cand"][0, 3]
+    assert first[0] == 0 and first[1] > 0   # both samples in the upper cell (reading R6)
+    assert last[0] > 0 and last[1] == 0     # both in the lower cell
+    np.testing.assert_array_equal(res["rgba"][0], first)
