@@ -1,0 +1,303 @@
+#!/usr/bin/env python3
+"""Throughput of the cached FastNeRF render on one MI355X.
+
+Workload (the paper-scale configuration): a k=768 position cache (D=8 radiance
+components, about 8% of voxels occupied by 28 ellipsoids and 12 thin shells),
+an l=384 direction cache, a 40-view orbit at radius 4 rendered at 800x800 with
+N=192 samples inside the box, eps=1e-4, nearest position lookup, bilinear
+direction lookup, 8^3 occupancy bricks, FP32 cache. One step renders the whole
+orbit, one persistent launch per view. Inputs are synthetic (seeded) and
+resident in HBM before timing starts.
+
+The JSON line also carries: per-frame p50/p99 latency, the same orbit with FP16
+and FP8 caches, the roofline of the render kernel (algorithmic bytes per launch
+over its measured duration) and the FP64 CPU oracle timed on a bounded sample
+of the same workload (which also gives the algorithmic byte count and a sampled
+parity check).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_render_f32_paper_scale_pmc.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_10380_amd", "csrc", f)
+                  for f in ("fastnerf_kernels.hip", "fastnerf_device.h")]
+
+
+def kernel_digest():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def build_caches(spec, storages, want_sparse, device):
+    """Generates the scene slab by slab on the GPU and uploads it to one cache
+    per storage format; optionally keeps a brick-sparse host copy."""
+    import paper_2103_10380_amd as fn
+    import synth
+    p = synth.draw(spec)
+    beta = synth.beta_table(p)
+    caches = {}
+    for st in storages:
+        desc = fn.make_desc(spec.k, spec.D, spec.l, storage=st, brick=8,
+                            sample_mode=fn.IN_BOX)
+        caches[st] = fn.Cache.create_empty(desc, beta)
+    k, sb = spec.k, 8
+    if "fp8" in caches:  # per-channel scales need the whole cache first
+        for z0 in range(0, k, sb):
+            if z0 % (16 * sb) == 0:
+                log(f"scan slab z0={z0}/{k}")
+            sig = synth.density(p, z0, sb, device)
+            u = synth.radiance(p, z0, sb, device)
+            caches["fp8"].scan_slab(z0, sig, u)
+    nb = k // sb
+    slot = np.full(nb ** 3, -1, np.int32) if want_sparse else None
+    ss, su, n, occ_vox = [], [], 0, 0
+    for z0 in range(0, k, sb):
+        if z0 % (16 * sb) == 0:
+            log(f"upload slab z0={z0}/{k}")
+        sig = synth.density(p, z0, sb, device)
+        u = synth.radiance(p, z0, sb, device)
+        occ_vox += int((sig > 0).sum())
+        for c in caches.values():
+            c.upload_slab(z0, sig, u)
+        if want_sparse:
+            idx, s1, u1 = synth.brick_sparse_slab(sig, u, sb)
+            slot[(z0 // sb) * nb * nb + idx] = np.arange(n, n + len(idx), dtype=np.int32)
+            n += len(idx)
+            ss.append(s1)
+            su.append(u1)
+    for c in caches.values():
+        c.finalize()
+    sparse = None
+    if want_sparse:
+        sparse = (sb, slot, np.concatenate(ss), np.concatenate(su))
+    return p, beta, caches, sparse, occ_vox / k ** 3
+
+
+def time_orbit(fn, cache, views, N, eps, steps, warmup):
+    import torch
+    outs = [torch.empty((v.H, v.W, 4), dtype=torch.float32, device="cuda") for v in views]
+    for _ in range(warmup):
+        for v, o in zip(views, outs):
+            fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, out=o)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps * len(views))]
+    t0 = time.perf_counter()
+    q = 0
+    for _ in range(steps):
+        for v, o in zip(views, outs):
+            evs[q][0].record()
+            fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, out=o)
+            evs[q][1].record()
+            q += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    frame_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    return wall, frame_ms, outs
+
+
+def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, seed=11):
+    """The FP64 oracle, single-threaded, on random pixels of every view; stops
+    at the time budget after completing a whole view."""
+    import oracle
+    sb, slot, ss, su = sparse
+    sc = oracle.Scene(beta, k=spec.k, sparse=(sb, slot, ss, su), in_box=True, occ_brick=8)
+    rng = np.random.default_rng(seed)
+    res, done_views, rays, t_cpu = [], 0, 0, 0.0
+    totals = dict(hit=0, occ_samples=0, rays=0)
+    for vi, v in enumerate(views):
+        pix = np.sort(rng.choice(v.H * v.W, pix_per_view, replace=False))
+        t0 = time.perf_counter()
+        r = oracle.render(sc, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, pix=pix)
+        t_cpu += time.perf_counter() - t0
+        res.append((vi, pix, r))
+        rays += len(pix)
+        for key in totals:
+            totals[key] += r["counts"][key]
+        done_views += 1
+        if t_cpu >= seconds:
+            break
+    return sc, res, rays, t_cpu, totals
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--views", type=int, default=40)
+    ap.add_argument("--k", type=int, default=768)
+    ap.add_argument("--no-variants", action="store_true", help="FP32 cache only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-pixels", type=int, default=2048, help="oracle pixels per view")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build "
+              "renders on a single MI355X; multi-GPU sharding is a design note only)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2103_10380_amd as fn
+    import synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    fn.lib()
+
+    N, eps = 192, 1e-4
+    spec = synth.paper_scene_spec(k=args.k)
+    views = synth.paper_orbit(args.views)
+    storages = ["f32"] if args.no_variants else ["f32", "f16", "fp8"]
+    t0 = time.perf_counter()
+    p, beta, caches, sparse, occ = build_caches(spec, storages, not args.no_cpu, "cuda")
+    torch.cuda.synchronize()
+    log(f"scene k={spec.k} occupancy {occ:.4f}, caches {storages} built in "
+        f"{time.perf_counter() - t0:.1f}s; resident "
+        f"{sum(c.resident_bytes for c in caches.values()) / 2**30:.1f} GiB")
+
+    results = {}
+    outs_f32 = None
+    for st in storages:
+        wall, frame_ms, outs = time_orbit(fn, caches[st], views, N, eps, args.steps,
+                                          args.warmup)
+        rays = args.steps * sum(v.H * v.W for v in views)
+        results[st] = dict(wall=wall, frame_ms=frame_ms, mrays=rays / wall / 1e6)
+        if st == "f32":
+            outs_f32 = outs
+        else:
+            results[st]["outs"] = outs
+        log(f"{st}: {results[st]['mrays']:.1f} Mrays/s, frame p50 "
+            f"{np.percentile(frame_ms, 50):.3f} ms p99 {np.percentile(frame_ms, 99):.3f} ms")
+
+    r32 = results["f32"]
+    frame_ms = r32["frame_ms"]
+    line = {
+        "metric": "Mrays/s at 800x800, cached render (paper-scale cache, FP32)",
+        "value": round(r32["mrays"], 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["wall"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"paper-scale cached render: k={spec.k}^3 position cache, D=8, "
+                         f"l=384 direction cache, {occ * 100:.1f}% voxels occupied "
+                         "(28 ellipsoids + 12 shells, seed 1), "
+                         f"{args.views}-view orbit r=4 el=0.5 at 800x800, N=192 samples in "
+                         "the box, eps=1e-4, nearest position / bilinear direction lookup, "
+                         "8^3 occupancy bricks, FP32 cache"),
+            "views_per_step": args.views, "width": 800, "height": 800, "N": N,
+        },
+        "fps": round(1e3 / float(np.mean(frame_ms)), 1),
+        "frame_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
+        "frame_ms_p99": round(float(np.percentile(frame_ms, 99)), 4),
+    }
+
+    # ---------------------------------------------------------------- oracle leg
+    units = None
+    if not args.no_cpu:
+        sc, res, rays, t_cpu, totals = oracle_sample(beta, sparse, spec, views, N, eps,
+                                                     args.cpu_pixels, args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": round(rays / t_cpu / 1e6, 5), "unit": "Mrays/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"{rays} random pixels ({args.cpu_pixels} per view over "
+                       f"{len(res)} views) of the same workload, FP64 single-threaded, "
+                       f"{t_cpu:.1f} s"),
+        }
+        # algorithmic bytes per launch: records of samples in occupied bricks,
+        # the four direction cells per hit ray, the RGBA write
+        stride, payload = caches["f32"].record_bytes
+        frac = totals["rays"] / rays
+        pix_total = sum(views[vi].H * views[vi].W for vi, _, _ in res)
+        scale = pix_total / totals["rays"] / len(res)
+        occ_per_view = totals["occ_samples"] * scale
+        hit_per_view = totals["hit"] * scale
+        units = dict(occ_samples=occ_per_view, hit_rays=hit_per_view,
+                     rays=pix_total / len(res))
+        # sampled parity of the timed renders
+        import oracle
+        worst, fails, checked, psnr_in = 0.0, 0, 0, {}
+        for vi, pix, r in res:
+            g = outs_f32[vi].reshape(-1, 4)[torch.as_tensor(pix, device="cuda")].cpu().numpy()
+            err, ok = oracle.matches(g.astype(np.float64), r, 1e-4)
+            unchecked = (r["flags"] & oracle.UNCHECKED) != 0
+            fails += int((~ok & ~unchecked).sum())
+            checked += int((~unchecked).sum())
+            worst = max(worst, float(err[~unchecked].max()))
+        line["parity"] = {"pixels": checked, "max_abs_err": worst, "failing": fails,
+                          "tol": 1e-4, "reference": "FP64 oracle, FP32 cache"}
+        for st in storages:
+            if st == "f32":
+                continue
+            errs, mse = [], []
+            for vi, pix, r in res:
+                g = results[st]["outs"][vi].reshape(-1, 4)[
+                    torch.as_tensor(pix, device="cuda")].cpu().numpy().astype(np.float64)
+                err, _ = oracle.matches(g, r, 1.0)
+                errs.append(err.max())
+                mse.append(np.mean((g[:, :3] - r["rgba"][:, :3]) ** 2))
+            m = float(np.mean(mse))
+            psnr_in[st] = dict(max_abs_err=float(max(errs)),
+                               psnr_db=(float("inf") if m == 0 else 10 * np.log10(1 / m)))
+        _ = frac
+    # ---------------------------------------------------------------- roofline
+    if units is not None:
+        stride, payload = caches["f32"].record_bytes
+        D = spec.D
+        alg_bytes = units["occ_samples"] * payload + units["hit_rays"] * 4 * D * 4 + \
+            units["rays"] * 16
+        avg_s = float(np.mean(frame_ms)) / 1e3
+        achieved = alg_bytes / avg_s / 1e9
+        traffic = None
+        if os.path.exists(PMC_SUMMARY):
+            pmc = json.load(open(PMC_SUMMARY))
+            if pmc.get("kernel_digest") == kernel_digest():
+                traffic = pmc.get("hbm_bytes_per_launch")
+        line["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                            "kernel": "k_render<FP32, D<=8, nearest>",
+                            "algorithmic_bytes_per_launch": round(alg_bytes),
+                            "occupied_samples_per_launch": round(units["occ_samples"]),
+                            "record_payload_bytes": payload, "record_stride_bytes": stride}
+    variants = {}
+    for st in storages:
+        r = results[st]
+        variants[st] = {"mrays_per_s": round(r["mrays"], 2),
+                        "fps": round(1e3 / float(np.mean(r["frame_ms"])), 1),
+                        "frame_ms_p50": round(float(np.percentile(r["frame_ms"], 50)), 4),
+                        "frame_ms_p99": round(float(np.percentile(r["frame_ms"], 99)), 4),
+                        "speedup_vs_f32": round(r["mrays"] / r32["mrays"], 3)}
+        if not args.no_cpu and st != "f32":
+            variants[st].update({k2: round(v2, 6) for k2, v2 in psnr_in[st].items()})
+    line["variants"] = variants
+    line["kernel_digest"] = kernel_digest()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * fastnerf.h -- C ABI of the MI355X (gfx950) FastNeRF cached renderer.
+ *
+ * The library renders novel views from a factorised FastNeRF cache (Garbin et
+ * al., "FastNeRF: High-Fidelity Neural Rendering at 200FPS"):
+ *   - a position cache of k^3 voxels over a box V, each holding a density sigma
+ *     and a deep radiance map of D components (u_i, v_i, w_i)    [Sec. 3.2 Eq. 3, Sec. 3.3]
+ *   - a direction cache of l x l cells over theta in [0,pi] and phi in
+ *     [0,2pi), each holding D weights beta                       [Sec. 3.2 Eq. 4, Sec. 3.3]
+ * For each pixel a ray is cast, N samples are placed between the near and far
+ * bounds, the colour of a sample is beta . (u, v, w)               [Sec. 3.2 Eq. 5]
+ * and the samples are composited front to back with the transmittance [Sec. 3.1 Eq. 1],
+ * stopping once it falls below eps                                [supplementary S3].
+ *
+ * Conventions (readings of the paper, which does not fix them):
+ *   - Camera: pinhole intrinsics K (3x3 row-major) and camera-to-world c2w
+ *     (3x4 row-major, columns right, down, forward, eye: OpenCV axes). The ray
+ *     of pixel (x, y) has direction normalize(R K^-1 (x+1/2, y+1/2, 1)); row 0
+ *     is the top of the image.
+ *   - Samples: delta = (t1 - t0)/N, t_i = t0 + (i + 1/2) delta, where [t0, t1]
+ *     is [near, far] (FASTNERF_SAMPLES_NEAR_FAR) or [near, far] clipped to the
+ *     box (FASTNERF_SAMPLES_IN_BOX).
+ *   - Position cache values sit at voxel centres; the nearest voxel of a point
+ *     is the cell that contains it; outside the box the density is 0.
+ *     Trilinear lookups clamp corner indices to the grid.
+ *   - Direction: theta from +z, phi = atan2(y, x) in [0, 2pi); bilinear
+ *     lookups over cell centres are periodic in phi and clamped in theta.
+ *   - Compositing keeps the optical depth tau; it stops before a sample once
+ *     tau > ln(1/eps) (eps = 0: never). Output RGBA: RGB = C + exp(-tau) bg,
+ *     A = 1 - exp(-tau). No activation is applied to the colour.
+ *   - Storage: FP32, FP16 or BF16 (round to nearest even), or OCP FP8 E4M3
+ *     (round to nearest even, saturating) with one absmax scale per channel
+ *     (sigma and each of the 3D radiance channels): s = absmax/448 (1 if 0),
+ *     value = code * s. All arithmetic after the load is FP32.
+ *
+ * Errors: every call returns a fastnerf_status. Argument errors are reported
+ * synchronously, before anything is enqueued; fastnerf_last_error() returns a
+ * thread-local message for the last non-OK status. Render calls never
+ * synchronise: a device fault surfaces at the caller's next synchronisation.
+ * No C++ exception crosses the ABI.
+ *
+ * Memory: pointers marked "host or device" are classified with
+ * hipPointerGetAttributes; the library copies what it needs and the caller
+ * keeps ownership. Output buffers are caller-owned device memory.
+ */
+#ifndef FASTNERF_H
+#define FASTNERF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FASTNERF_OK = 0,
+  FASTNERF_EINVAL = -1,    /* bad argument or call out of order */
+  FASTNERF_ENOMEM = -2,    /* device or host allocation failed, or a request can never fit */
+  FASTNERF_EDEVICE = -3,   /* a HIP runtime call failed */
+  FASTNERF_EBUSY = -4,     /* queue full, try again */
+  FASTNERF_ECANCELED = -5, /* the request was cancelled */
+  FASTNERF_ESHUTDOWN = -6, /* the server is shutting down */
+  FASTNERF_ETIMEDOUT = -7  /* a wait ran out of time */
+} fastnerf_status;
+
+typedef enum { FASTNERF_F32 = 0, FASTNERF_F16 = 1, FASTNERF_BF16 = 2, FASTNERF_FP8_E4M3 = 3 } fastnerf_dtype;
+typedef enum { FASTNERF_NEAREST = 0, FASTNERF_LINEAR = 1 } fastnerf_interp;
+typedef enum { FASTNERF_SAMPLES_NEAR_FAR = 0, FASTNERF_SAMPLES_IN_BOX = 1 } fastnerf_sample_mode;
+
+typedef struct fastnerf_cache_s *fastnerf_cache;
+typedef struct fastnerf_server_s *fastnerf_server;
+
+typedef struct {
+  int32_t k;                 /* voxels per axis, 1..4096 */
+  int32_t D;                 /* components, 1..16 */
+  int32_t l;                 /* direction cells per angle, 1..4096 */
+  float bbox_min[3], bbox_max[3];
+  fastnerf_dtype storage;    /* position-cache storage; beta is FP32 */
+  fastnerf_interp pos_interp, dir_interp;
+  int32_t brick;             /* occupancy brick edge in voxels (power of two, k % brick == 0);
+                                0 = no empty-space skipping */
+  fastnerf_sample_mode sample_mode;
+  float background[3];
+} fastnerf_cache_desc;
+
+/* ---------------------------------------------------------------- caches */
+
+/* Builds a cache from FP32 arrays (host or device): sigma[k][k][k] (index
+ * (z*k + y)*k + x), u[k][k][k][D][3], beta[l][l][D] (theta row, phi column).
+ * Quantises to desc->storage, builds the occupancy bitgrid (dilated by one
+ * voxel for trilinear lookups) and returns a handle that is immutable and may
+ * be rendered from several streams at once. Work is enqueued on `stream`; the
+ * call returns after the input arrays have been consumed. [Sec. 3.3] */
+fastnerf_status fastnerf_cache_create(const fastnerf_cache_desc *desc, const float *sigma,
+                                      const float *u, const float *beta, hipStream_t stream,
+                                      fastnerf_cache *out);
+
+/* Slab-wise construction for caches larger than host memory or built on the
+ * device: create_empty, then (FP8 only) scan_slab for every slab so that the
+ * per-channel scales are known, then upload_slab for every slab, then
+ * finalize. A slab is nz consecutive z layers starting at z0, laid out like
+ * the full arrays. */
+fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc *desc, const float *beta,
+                                            hipStream_t stream, fastnerf_cache *out);
+fastnerf_status fastnerf_cache_scan_slab(fastnerf_cache cache, int32_t z0, int32_t nz,
+                                         const float *sigma, const float *u, hipStream_t stream);
+fastnerf_status fastnerf_cache_upload_slab(fastnerf_cache cache, int32_t z0, int32_t nz,
+                                           const float *sigma, const float *u, hipStream_t stream);
+fastnerf_status fastnerf_cache_finalize(fastnerf_cache cache, hipStream_t stream);
+
+/* Device bytes held by the cache (records, direction cache, bitgrid, scales). */
+fastnerf_status fastnerf_cache_bytes(fastnerf_cache cache, uint64_t *resident);
+/* Bytes per stored voxel record (padded) and of its payload, (1+3D)*size(storage). */
+fastnerf_status fastnerf_cache_record_bytes(fastnerf_cache cache, int32_t *stride,
+                                            int32_t *payload);
+/* Dequantised copy of the stored cache into caller device buffers
+ * sigma[k^3] and u[k^3*D*3] (FP32), and the per-channel scales (host, 1+3D
+ * floats, may be NULL). Synchronises `stream`. Test hook. */
+fastnerf_status fastnerf_cache_readback(fastnerf_cache cache, float *sigma, float *u,
+                                        float *scales, hipStream_t stream);
+/* Occupancy bitgrid (host copy): nbricks^3 bits, brick index (bz*n + by)*n + bx,
+ * bit b in word b/32. words must hold ceil(n^3/32) entries. */
+fastnerf_status fastnerf_cache_occupancy(fastnerf_cache cache, uint32_t *words, int32_t *n);
+/* Waits for renders that use the cache, then frees it. */
+fastnerf_status fastnerf_cache_destroy(fastnerf_cache cache);
+
+/* ---------------------------------------------------------------- rendering */
+
+/* Renders one H x W view into out (device, float[H][W][4]). N in [1, 4096],
+ * near < far, eps in [0, 1). One persistent launch on `stream`; asynchronous.
+ * [Sec. 3.1 Eq. 1, Sec. 3.2 Eq. 5, Sec. 4] */
+fastnerf_status fastnerf_render(fastnerf_cache cache, const float K[9], const float c2w[12],
+                                int32_t H, int32_t W, float near, float far, int32_t N, float eps,
+                                float *out, hipStream_t stream);
+
+/* Renders nviews views of one cache in a single persistent launch. K, c2w,
+ * H, W, near, far and out are host arrays of nviews entries (out[i] is a
+ * device buffer of H[i]*W[i]*4 floats). */
+fastnerf_status fastnerf_render_batch(fastnerf_cache cache, int32_t nviews, const float *K,
+                                      const float *c2w, const int32_t *H, const int32_t *W,
+                                      const float *near, const float *far, int32_t N, float eps,
+                                      float *const *out, hipStream_t stream);
+
+/* Test hook: the kernel's own lookups. pts and dirs are device arrays of n
+ * points / unit directions (3 floats each); sigma_u receives n*(1+3D) floats
+ * (sigma then u[D][3]), beta n*D floats (device). */
+fastnerf_status fastnerf_debug_lookup(fastnerf_cache cache, int32_t n, const float *pts,
+                                      const float *dirs, float *sigma_u, float *beta,
+                                      hipStream_t stream);
+
+/* ---------------------------------------------------------------- memory model */
+
+/* The paper's cache-size model (supplementary S4, Eq. S2):
+ * alpha * (D*s_uvw + s_sigma) * k^3 + D * s_beta * l^2 bytes, where s_uvw is
+ * the size of one stored (u_i, v_i, w_i) triple, s_sigma of a density and
+ * s_beta of a weight, and alpha in [0, 1] is the occupied fraction. */
+double fastnerf_model_bytes(double alpha, int64_t k, int64_t l, int32_t D, double s_sigma,
+                            double s_uvw, double s_beta);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A continuous-batching render server over resident caches. Requests are
+ * admitted while their output fits the arena (bytes of device memory the
+ * server owns) and fewer than max_inflight are running; every step renders
+ * all admitted requests' tiles in one persistent launch, replayed as a HIP
+ * graph. Requests that arrive while others run join at the next step. */
+fastnerf_status fastnerf_server_create(const fastnerf_cache *scenes, int32_t nscenes,
+                                       uint64_t arena_bytes, int32_t max_inflight,
+                                       fastnerf_server *out);
+/* Non-blocking. EBUSY when the queue is full, ENOMEM when the request can
+ * never fit the arena, ESHUTDOWN after destroy began. */
+fastnerf_status fastnerf_serve_submit(fastnerf_server server, int32_t scene, const float K[9],
+                                      const float c2w[12], int32_t H, int32_t W, float near,
+                                      float far, int32_t N, float eps, uint64_t *ticket);
+/* Waits up to timeout_us (-1: forever) for a ticket. On OK, *out_device points
+ * at the H*W*4 floats of the result (valid until release) and *latency_ms is
+ * submit-to-completion time. */
+fastnerf_status fastnerf_serve_wait(fastnerf_server server, uint64_t ticket, int64_t timeout_us,
+                                    const float **out_device, double *latency_ms);
+fastnerf_status fastnerf_serve_release(fastnerf_server server, uint64_t ticket);
+fastnerf_status fastnerf_serve_cancel(fastnerf_server server, uint64_t ticket);
+/* Counters: steps run, requests completed, max requests in one step. */
+fastnerf_status fastnerf_server_stats(fastnerf_server server, uint64_t *steps,
+                                      uint64_t *completed, uint64_t *max_batch);
+/* Drains running work, cancels queued requests, frees everything. */
+fastnerf_status fastnerf_server_destroy(fastnerf_server server);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char *fastnerf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTNERF_H */

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) FastNeRF cached renderer.
+
+The compute path is the HIP library ``libfastnerf.so`` (C ABI in
+``include/fastnerf.h``); this package is its thin Python binding. PyTorch
+supplies device memory and streams only.
+"""
+from ._lib import (BF16, F16, F32, FP8, IN_BOX, LINEAR, NEAR_FAR, NEAREST, Cache,  # noqa: F401
+                   FastNeRFError, Server, debug_lookup, lib, make_desc, model_bytes,
+                   render, render_batch)

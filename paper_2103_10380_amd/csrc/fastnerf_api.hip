@@ -1,0 +1,593 @@
+// Host side of the C ABI declared in include/fastnerf.h: argument checks,
+// cache lifetime, per-stream launch state and kernel dispatch.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "fastnerf.h"
+#include "fastnerf_internal.h"
+#include "fastnerf_kernels.h"
+
+using namespace fnr;
+
+// ------------------------------------------------------------------ errors
+
+namespace fnr {
+
+static thread_local std::string g_err;
+
+fastnerf_status fail(fastnerf_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+fastnerf_status hip_fail(hipError_t e, const char *what) {
+  return fail(e == hipErrorOutOfMemory ? FASTNERF_ENOMEM : FASTNERF_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+}  // namespace fnr
+
+#define HIP_TRY(call)                                 \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+extern "C" const char *fastnerf_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ helpers
+
+namespace fnr {
+
+static int ilog2(uint64_t v) {
+  int r = 0;
+  while ((1ull << r) < v) ++r;
+  return r;
+}
+
+static bool is_device_ptr(const void *p) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+static bool finite_all(const float *v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(v[i])) return false;
+  return true;
+}
+
+// Per (device, stream) launch state: the self-resetting tile-queue counter and
+// a staging area for batched view descriptors. Allocated once per stream.
+struct StreamState {
+  unsigned *counter = nullptr;
+  DevView *views = nullptr;
+  DevView *views_host = nullptr;  // pinned
+  int cap = 0;
+  hipEvent_t staged = nullptr;    // last descriptor copy out of views_host
+};
+
+static std::mutex g_streams_mu;
+static std::map<std::pair<int, hipStream_t>, StreamState *> g_streams;
+
+fastnerf_status stream_state(hipStream_t s, StreamState **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_streams_mu);
+  auto key = std::make_pair(dev, s);
+  auto it = g_streams.find(key);
+  if (it != g_streams.end()) {
+    *out = it->second;
+    return FASTNERF_OK;
+  }
+  StreamState *st = new StreamState();
+  hipError_t e = hipMalloc(&st->counter, 2 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(st->counter, 0, 2 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete st;
+    return hip_fail(e, "stream state");
+  }
+  g_streams[key] = st;
+  *out = st;
+  return FASTNERF_OK;
+}
+
+fastnerf_status stream_views(StreamState *st, int n) {
+  if (n <= st->cap) return FASTNERF_OK;
+  HIP_TRY(hipEventSynchronize(st->staged));
+  if (st->views) HIP_TRY(hipFree(st->views));
+  if (st->views_host) HIP_TRY(hipHostFree(st->views_host));
+  st->views = nullptr;
+  st->views_host = nullptr;
+  st->cap = 0;
+  int cap = n < 64 ? 64 : n;
+  HIP_TRY(hipMalloc(&st->views, sizeof(DevView) * cap));
+  HIP_TRY(hipHostMalloc(&st->views_host, sizeof(DevView) * cap, hipHostMallocDefault));
+  st->cap = cap;
+  return FASTNERF_OK;
+}
+
+int persistent_grid(const fastnerf_cache_s *c, int total_tiles) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int> cu_blocks;  // (device, variant) -> blocks
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const bool lin = c->desc.pos_interp == FASTNERF_LINEAR;
+  const int variant = (int)c->desc.storage * 64 + (lin ? 32 : 0) + (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
+  int blocks;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_pair(dev, variant);
+    auto it = cu_blocks.find(key);
+    if (it == cu_blocks.end()) {
+      int cus = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          cus < 1)
+        cus = 1;
+      it = cu_blocks.emplace(key, cus * render_occupancy((int)c->desc.storage, lin, c->desc.D))
+               .first;
+    }
+    blocks = it->second;
+  }
+  const int need = (total_tiles + kBlock / kWave - 1) / (kBlock / kWave);
+  return need < blocks ? (need < 1 ? 1 : need) : blocks;
+}
+
+// View descriptor from K and c2w. R K^-1 is formed in double and rounded once.
+void make_view(const fastnerf_cache_s *c, const float K[9], const float c2w[12], int H, int W,
+               float near_, float far_, float *out, int tile_begin, DevView *v) {
+  const double a = K[0], b = K[1], cc = K[2], d = K[3], e = K[4], f = K[5], g = K[6], h = K[7],
+               i = K[8];
+  const double c00 = e * i - f * h, c01 = -(d * i - f * g), c02 = d * h - e * g;
+  const double det = a * c00 + b * c01 + cc * c02;
+  const double Ki[9] = {c00 / det, -(b * i - cc * h) / det, (b * f - cc * e) / det,
+                        c01 / det, (a * i - cc * g) / det,  -(a * f - cc * d) / det,
+                        c02 / det, -(a * h - b * g) / det,  (a * e - b * d) / det};
+  for (int r = 0; r < 3; ++r)
+    for (int col = 0; col < 3; ++col) {
+      double s = 0.0;
+      for (int q = 0; q < 3; ++q) s += (double)c2w[4 * r + q] * Ki[3 * q + col];
+      v->M[3 * r + col] = (float)s;
+    }
+  for (int r = 0; r < 3; ++r) {
+    v->o[r] = c2w[4 * r + 3];
+    v->og[r] = (float)(((double)c2w[4 * r + 3] - (double)c->desc.bbox_min[r]) * c->desc.k /
+                       ((double)c->desc.bbox_max[r] - (double)c->desc.bbox_min[r]));
+  }
+  v->near_ = near_;
+  v->far_ = far_;
+  v->H = H;
+  v->W = W;
+  v->tiles_x = (W + 7) / 8;
+  v->tile_begin = tile_begin;
+  v->tile_offset = 0;
+  v->scene = 0;
+  v->out = out;
+}
+
+fastnerf_status check_view(const float *K, const float *c2w, int H, int W, float near_,
+                                  float far_, const float *out) {
+  if (!K || !c2w || !out) return fail(FASTNERF_EINVAL, "null K, c2w or out");
+  if (H <= 0 || W <= 0 || H > 65536 || W > 65536)
+    return fail(FASTNERF_EINVAL, "image size %d x %d out of range", W, H);
+  if (!finite_all(K, 9) || !finite_all(c2w, 12)) return fail(FASTNERF_EINVAL, "non-finite camera");
+  const double det = (double)K[0] * ((double)K[4] * K[8] - (double)K[5] * K[7]) -
+                     (double)K[1] * ((double)K[3] * K[8] - (double)K[5] * K[6]) +
+                     (double)K[2] * ((double)K[3] * K[7] - (double)K[4] * K[6]);
+  if (det == 0.0) return fail(FASTNERF_EINVAL, "singular intrinsics");
+  if (!isfinite(near_) || !isfinite(far_) || !(near_ < far_))
+    return fail(FASTNERF_EINVAL, "need finite near < far");
+  return FASTNERF_OK;
+}
+
+DevCache dev_cache(const fastnerf_cache_s *c) {
+  DevCache d;
+  memset(&d, 0, sizeof d);
+  const fastnerf_cache_desc &ds = c->desc;
+  d.rec = c->rec;
+  d.beta = c->beta;
+  d.occ = c->desc.brick > 0 ? c->occ : nullptr;
+  d.scales = c->scales;
+  d.k = ds.k;
+  d.D = ds.D;
+  d.l = ds.l;
+  d.nbl = c->nbl;
+  d.nbo = c->nbo;
+  d.oshift = c->oshift;
+  d.rec_shift = c->rec_shift;
+  d.nchunk = c->nchunk;
+  d.kf = (float)ds.k;
+  for (int a = 0; a < 3; ++a) {
+    d.bmin[a] = ds.bbox_min[a];
+    d.bmax[a] = ds.bbox_max[a];
+    d.inv_h[a] = (float)((double)ds.k / ((double)ds.bbox_max[a] - (double)ds.bbox_min[a]));
+    d.bg[a] = ds.background[a];
+  }
+  d.th_scale = (float)(ds.l / M_PI);
+  d.ph_scale = (float)(ds.l / (2.0 * M_PI));
+  d.in_box = ds.sample_mode == FASTNERF_SAMPLES_IN_BOX;
+  d.dir_linear = ds.dir_interp == FASTNERF_LINEAR;
+  d.fmt = (int)ds.storage;
+  return d;
+}
+
+fastnerf_status check_render_params(int N, float eps) {
+  if (N < 1 || N > 4096) return fail(FASTNERF_EINVAL, "N = %d outside [1, 4096]", N);
+  if (!(eps >= 0.0f && eps < 1.0f)) return fail(FASTNERF_EINVAL, "eps outside [0, 1)");
+  return FASTNERF_OK;
+}
+
+float eps_limit(float eps) { return eps > 0.0f ? (float)log(1.0 / (double)eps) : INFINITY; }
+
+fastnerf_status enqueue_render(fastnerf_cache_s *c, const RenderArgs &a0, int total_tiles,
+                               StreamState *st, hipStream_t s) {
+  RenderArgs a = a0;
+  const int grid = persistent_grid(c, total_tiles);
+  a.counter = st->counter;
+  a.nwaves = (unsigned)grid * (kBlock / kWave);
+  a.total_tiles = total_tiles;
+  hipError_t e = launch_render((int)c->desc.storage, c->desc.pos_interp == FASTNERF_LINEAR, a,
+                               grid, s);
+  if (e != hipSuccess) return hip_fail(e, "render launch");
+  HIP_TRY(hipEventRecord(c->last_use, s));
+  return FASTNERF_OK;
+}
+
+}  // namespace fnr
+
+// ------------------------------------------------------------------ caches
+
+static fastnerf_status validate_desc(const fastnerf_cache_desc *d) {
+  if (!d) return fail(FASTNERF_EINVAL, "null descriptor");
+  if (d->k < 1 || d->k > 4096) return fail(FASTNERF_EINVAL, "k = %d outside [1, 4096]", d->k);
+  if (d->D < 1 || d->D > 16) return fail(FASTNERF_EINVAL, "D = %d outside [1, 16]", d->D);
+  if (d->l < 1 || d->l > 4096) return fail(FASTNERF_EINVAL, "l = %d outside [1, 4096]", d->l);
+  if ((unsigned)d->storage > 3u) return fail(FASTNERF_EINVAL, "unknown storage format");
+  if ((unsigned)d->pos_interp > 1u || (unsigned)d->dir_interp > 1u)
+    return fail(FASTNERF_EINVAL, "unknown interpolation mode");
+  if ((unsigned)d->sample_mode > 1u) return fail(FASTNERF_EINVAL, "unknown sample mode");
+  if (d->brick < 0 || (d->brick > 0 && ((d->brick & (d->brick - 1)) || d->k % d->brick)))
+    return fail(FASTNERF_EINVAL, "brick %d must be 0 or a power of two dividing k = %d",
+                d->brick, d->k);
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(d->bbox_min[a]) || !isfinite(d->bbox_max[a]) ||
+        !(d->bbox_min[a] < d->bbox_max[a]) || !isfinite(d->background[a]))
+      return fail(FASTNERF_EINVAL, "bad bounding box or background");
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc *desc,
+                                                       const float *beta, hipStream_t stream,
+                                                       fastnerf_cache *out) {
+  fastnerf_status st = validate_desc(desc);
+  if (st != FASTNERF_OK) return st;
+  if (!beta || !out) return fail(FASTNERF_EINVAL, "null beta or out");
+  *out = nullptr;
+  fastnerf_cache_s *c = new (std::nothrow) fastnerf_cache_s();
+  if (!c) return fail(FASTNERF_ENOMEM, "host allocation");
+  c->desc = *desc;
+  const int sz = desc->storage == FASTNERF_F32 ? 4 : desc->storage == FASTNERF_FP8_E4M3 ? 1 : 2;
+  c->payload = (1 + 3 * desc->D) * sz;
+  int stride = 16;
+  while (stride < c->payload) stride <<= 1;
+  c->stride = stride;
+  c->rec_shift = ilog2((uint64_t)stride);
+  c->nchunk = (c->payload + 15) / 16;
+  c->nbl = (desc->k + 7) / 8;
+  if (desc->brick > 0) {
+    c->oshift = ilog2((uint64_t)desc->brick);
+    c->nbo = desc->k / desc->brick;
+  } else {
+    c->oshift = 0;
+    c->nbo = 0;
+  }
+  const uint64_t nrec = (uint64_t)c->nbl * c->nbl * c->nbl * 512ull;
+  const uint64_t rec_bytes = nrec * (uint64_t)stride;
+  const uint64_t beta_bytes = (uint64_t)desc->l * desc->l * desc->D * sizeof(float);
+  const uint64_t nbits = (uint64_t)c->nbo * c->nbo * c->nbo;
+  const uint64_t occ_bytes = ((nbits + 31) / 32 + 1) * 4;
+  const int nch = 1 + 3 * desc->D;
+  hipError_t e = hipMalloc(&c->rec, rec_bytes);
+  if (e == hipSuccess) e = hipMalloc(&c->beta, beta_bytes);
+  if (e == hipSuccess) e = hipMalloc(&c->occ, occ_bytes);
+  if (e == hipSuccess) e = hipMalloc(&c->scales, sizeof(float) * nch);
+  if (e == hipSuccess) e = hipMalloc(&c->amax, sizeof(unsigned) * nch);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->last_use, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMemsetAsync(c->rec, 0, rec_bytes, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->occ, 0, occ_bytes, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->amax, 0, sizeof(unsigned) * nch, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->beta, beta, beta_bytes, hipMemcpyDefault, stream);
+  if (e == hipSuccess && desc->storage != FASTNERF_FP8_E4M3) {
+    std::vector<float> ones(nch, 1.0f);
+    e = hipMemcpyAsync(c->scales, ones.data(), sizeof(float) * nch, hipMemcpyHostToDevice,
+                       stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    c->scales_ready = true;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    fastnerf_status r = hip_fail(e, "cache allocation");
+    fastnerf_cache_destroy(c);
+    return r;
+  }
+  c->resident = rec_bytes + beta_bytes + occ_bytes + sizeof(float) * nch;
+  c->occ_bytes = occ_bytes;
+  (void)hipGetDevice(&c->device);
+  *out = c;
+  return FASTNERF_OK;
+}
+
+// Runs fn(sigma_dev, u_dev, z0, nz) over the slab, staging host input through
+// device memory in chunks of layers.
+template <class Fn>
+static fastnerf_status for_device_slab(fastnerf_cache_s *c, int z0, int nz, const float *sigma,
+                                       const float *u, hipStream_t s, Fn fn) {
+  const int k = c->desc.k, n3 = 3 * c->desc.D;
+  const bool dev = is_device_ptr(sigma);
+  if (dev != is_device_ptr(u)) return fail(FASTNERF_EINVAL, "sigma and u must both be host or device");
+  if (dev) return fn(sigma, u, z0, nz);
+  const uint64_t layer = (uint64_t)k * k;
+  int chunk = (int)((256ull << 20) / (layer * (1 + n3) * 4));
+  if (chunk < 1) chunk = 1;
+  if (chunk > nz) chunk = nz;
+  float *ds = nullptr, *du = nullptr;
+  hipError_t e = hipMalloc(&ds, layer * chunk * 4);
+  if (e == hipSuccess) e = hipMalloc(&du, layer * chunk * n3 * 4);
+  fastnerf_status st = FASTNERF_OK;
+  for (int z = 0; e == hipSuccess && st == FASTNERF_OK && z < nz; z += chunk) {
+    const int m = nz - z < chunk ? nz - z : chunk;
+    e = hipMemcpyAsync(ds, sigma + (uint64_t)z * layer, layer * m * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(du, u + (uint64_t)z * layer * n3, layer * m * n3 * 4,
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) st = fn(ds, du, z0 + z, m);
+    if (e == hipSuccess && st == FASTNERF_OK) e = hipStreamSynchronize(s);
+  }
+  if (ds) (void)hipFree(ds);
+  if (du) (void)hipFree(du);
+  if (e != hipSuccess) return hip_fail(e, "slab staging");
+  return st;
+}
+
+static fastnerf_status check_slab(fastnerf_cache_s *c, int z0, int nz, const float *sigma,
+                                  const float *u) {
+  if (!c) return fail(FASTNERF_EINVAL, "null cache");
+  if (c->finalized) return fail(FASTNERF_EINVAL, "cache already finalized");
+  if (!sigma || !u) return fail(FASTNERF_EINVAL, "null sigma or u");
+  if (z0 < 0 || nz < 1 || z0 + nz > c->desc.k)
+    return fail(FASTNERF_EINVAL, "slab [%d, %d) outside [0, %d)", z0, z0 + nz, c->desc.k);
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_cache_scan_slab(fastnerf_cache c, int32_t z0, int32_t nz,
+                                                    const float *sigma, const float *u,
+                                                    hipStream_t s) {
+  fastnerf_status st = check_slab(c, z0, nz, sigma, u);
+  if (st != FASTNERF_OK) return st;
+  if (c->desc.storage != FASTNERF_FP8_E4M3) return FASTNERF_OK;
+  if (c->scales_ready) return fail(FASTNERF_EINVAL, "scan after the first upload");
+  return for_device_slab(c, z0, nz, sigma, u, s,
+                         [&](const float *ds, const float *du, int, int m) -> fastnerf_status {
+                           hipError_t e = launch_absmax(ds, du, (int64_t)m * c->desc.k * c->desc.k,
+                                                        c->desc.D, c->amax, s);
+                           return e == hipSuccess ? FASTNERF_OK : hip_fail(e, "absmax");
+                         });
+}
+
+extern "C" fastnerf_status fastnerf_cache_upload_slab(fastnerf_cache c, int32_t z0, int32_t nz,
+                                                      const float *sigma, const float *u,
+                                                      hipStream_t s) {
+  fastnerf_status st = check_slab(c, z0, nz, sigma, u);
+  if (st != FASTNERF_OK) return st;
+  if (!c->scales_ready) {
+    hipError_t e = launch_make_scales(c->amax, 1 + 3 * c->desc.D, c->scales, s);
+    if (e != hipSuccess) return hip_fail(e, "scales");
+    c->scales_ready = true;
+  }
+  const DevCache dc = dev_cache(c);
+  return for_device_slab(c, z0, nz, sigma, u, s,
+                         [&](const float *ds, const float *du, int zz, int m) -> fastnerf_status {
+                           hipError_t e = launch_pack((int)c->desc.storage, ds, du, zz, m, dc, s);
+                           return e == hipSuccess ? FASTNERF_OK : hip_fail(e, "pack");
+                         });
+}
+
+extern "C" fastnerf_status fastnerf_cache_finalize(fastnerf_cache c, hipStream_t s) {
+  if (!c) return fail(FASTNERF_EINVAL, "null cache");
+  if (c->finalized) return fail(FASTNERF_EINVAL, "cache already finalized");
+  if (!c->scales_ready) return fail(FASTNERF_EINVAL, "no slab was uploaded");
+  if (c->desc.brick > 0) {
+    const DevCache dc = dev_cache(c);
+    hipError_t e = launch_occupancy((int)c->desc.storage, dc,
+                                    c->desc.pos_interp == FASTNERF_LINEAR ? 1 : 0, c->occ, s);
+    if (e != hipSuccess) return hip_fail(e, "occupancy");
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  c->finalized = true;
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_cache_create(const fastnerf_cache_desc *desc,
+                                                 const float *sigma, const float *u,
+                                                 const float *beta, hipStream_t s,
+                                                 fastnerf_cache *out) {
+  if (!sigma || !u) return fail(FASTNERF_EINVAL, "null sigma or u");
+  if (!out) return fail(FASTNERF_EINVAL, "null out");
+  fastnerf_cache c = nullptr;
+  fastnerf_status st = fastnerf_cache_create_empty(desc, beta, s, &c);
+  if (st != FASTNERF_OK) return st;
+  st = fastnerf_cache_scan_slab(c, 0, desc->k, sigma, u, s);
+  if (st == FASTNERF_OK) st = fastnerf_cache_upload_slab(c, 0, desc->k, sigma, u, s);
+  if (st == FASTNERF_OK) st = fastnerf_cache_finalize(c, s);
+  if (st != FASTNERF_OK) {
+    std::string msg = g_err;
+    fastnerf_cache_destroy(c);
+    g_err = msg;
+    return st;
+  }
+  *out = c;
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_cache_bytes(fastnerf_cache c, uint64_t *resident) {
+  if (!c || !resident) return fail(FASTNERF_EINVAL, "null argument");
+  *resident = c->resident;
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_cache_record_bytes(fastnerf_cache c, int32_t *stride,
+                                                       int32_t *payload) {
+  if (!c || !stride || !payload) return fail(FASTNERF_EINVAL, "null argument");
+  *stride = c->stride;
+  *payload = c->payload;
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_cache_readback(fastnerf_cache c, float *sigma, float *u,
+                                                   float *scales, hipStream_t s) {
+  if (!c || !sigma || !u) return fail(FASTNERF_EINVAL, "null argument");
+  if (!c->finalized) return fail(FASTNERF_EINVAL, "cache not finalized");
+  if (!is_device_ptr(sigma) || !is_device_ptr(u))
+    return fail(FASTNERF_EINVAL, "readback buffers must be device memory");
+  hipError_t e = launch_readback((int)c->desc.storage, dev_cache(c), sigma, u, s);
+  if (e != hipSuccess) return hip_fail(e, "readback");
+  if (scales)
+    HIP_TRY(hipMemcpyAsync(scales, c->scales, sizeof(float) * (1 + 3 * c->desc.D),
+                           hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_cache_occupancy(fastnerf_cache c, uint32_t *words,
+                                                    int32_t *n) {
+  if (!c || !n) return fail(FASTNERF_EINVAL, "null argument");
+  *n = c->nbo;
+  if (c->desc.brick == 0 || !words) return FASTNERF_OK;
+  const uint64_t nbits = (uint64_t)c->nbo * c->nbo * c->nbo;
+  HIP_TRY(hipMemcpy(words, c->occ, (nbits + 31) / 32 * 4, hipMemcpyDeviceToHost));
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_cache_destroy(fastnerf_cache c) {
+  if (!c) return fail(FASTNERF_EINVAL, "null cache");
+  if (c->last_use) {
+    (void)hipEventSynchronize(c->last_use);
+    (void)hipEventDestroy(c->last_use);
+  }
+  if (c->rec) (void)hipFree(c->rec);
+  if (c->beta) (void)hipFree(c->beta);
+  if (c->occ) (void)hipFree(c->occ);
+  if (c->scales) (void)hipFree(c->scales);
+  if (c->amax) (void)hipFree(c->amax);
+  delete c;
+  return FASTNERF_OK;
+}
+
+// ------------------------------------------------------------------ rendering
+
+extern "C" fastnerf_status fastnerf_render(fastnerf_cache c, const float K[9],
+                                           const float c2w[12], int32_t H, int32_t W, float near_,
+                                           float far_, int32_t N, float eps, float *out,
+                                           hipStream_t s) {
+  if (!c) return fail(FASTNERF_EINVAL, "null cache");
+  if (!c->finalized) return fail(FASTNERF_EINVAL, "cache not finalized");
+  fastnerf_status st = check_view(K, c2w, H, W, near_, far_, out);
+  if (st == FASTNERF_OK) st = check_render_params(N, eps);
+  if (st != FASTNERF_OK) return st;
+  StreamState *ss = nullptr;
+  st = stream_state(s, &ss);
+  if (st != FASTNERF_OK) return st;
+  RenderArgs a;
+  memset(&a, 0, sizeof a);
+  a.c = dev_cache(c);
+  make_view(c, K, c2w, H, W, near_, far_, out, 0, &a.v0);
+  a.v0.N = N;
+  a.v0.lim = eps_limit(eps);
+  a.views = nullptr;
+  a.nviews = 1;
+  const int tiles = ((W + 7) / 8) * ((H + 7) / 8);
+  return enqueue_render(c, a, tiles, ss, s);
+}
+
+extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nviews,
+                                                 const float *K, const float *c2w,
+                                                 const int32_t *H, const int32_t *W,
+                                                 const float *near_, const float *far_,
+                                                 int32_t N, float eps, float *const *out,
+                                                 hipStream_t s) {
+  if (!c) return fail(FASTNERF_EINVAL, "null cache");
+  if (!c->finalized) return fail(FASTNERF_EINVAL, "cache not finalized");
+  if (nviews < 1) return fail(FASTNERF_EINVAL, "nviews = %d", nviews);
+  if (!K || !c2w || !H || !W || !near_ || !far_ || !out)
+    return fail(FASTNERF_EINVAL, "null view array");
+  fastnerf_status st = check_render_params(N, eps);
+  if (st != FASTNERF_OK) return st;
+  int64_t total = 0;
+  for (int v = 0; v < nviews; ++v) {
+    st = check_view(K + 9 * v, c2w + 12 * v, H[v], W[v], near_[v], far_[v], out[v]);
+    if (st != FASTNERF_OK) return fail(st, "view %d: %s", v, g_err.c_str());
+    total += (int64_t)((W[v] + 7) / 8) * ((H[v] + 7) / 8);
+  }
+  if (total > (int64_t)0x7FFFFFFF) return fail(FASTNERF_EINVAL, "too many tiles in one batch");
+  StreamState *ss = nullptr;
+  st = stream_state(s, &ss);
+  if (st == FASTNERF_OK) st = stream_views(ss, nviews);
+  if (st != FASTNERF_OK) return st;
+  HIP_TRY(hipEventSynchronize(ss->staged));  // the previous batch's descriptors were copied
+  int tb = 0;
+  for (int v = 0; v < nviews; ++v) {
+    make_view(c, K + 9 * v, c2w + 12 * v, H[v], W[v], near_[v], far_[v], out[v], tb,
+              ss->views_host + v);
+    ss->views_host[v].N = N;
+    ss->views_host[v].lim = eps_limit(eps);
+    tb += ((W[v] + 7) / 8) * ((H[v] + 7) / 8);
+  }
+  HIP_TRY(hipMemcpyAsync(ss->views, ss->views_host, sizeof(DevView) * nviews,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(ss->staged, s));
+  RenderArgs a;
+  memset(&a, 0, sizeof a);
+  a.c = dev_cache(c);
+  a.views = ss->views;
+  a.nviews = nviews;
+  return enqueue_render(c, a, (int)total, ss, s);
+}
+
+extern "C" fastnerf_status fastnerf_debug_lookup(fastnerf_cache c, int32_t n, const float *pts,
+                                                 const float *dirs, float *sigma_u, float *beta,
+                                                 hipStream_t s) {
+  if (!c) return fail(FASTNERF_EINVAL, "null cache");
+  if (!c->finalized) return fail(FASTNERF_EINVAL, "cache not finalized");
+  if (n < 0) return fail(FASTNERF_EINVAL, "n < 0");
+  if (n == 0) return FASTNERF_OK;
+  if ((pts == nullptr) != (sigma_u == nullptr) || (dirs == nullptr) != (beta == nullptr))
+    return fail(FASTNERF_EINVAL, "inputs and outputs must be given in pairs");
+  hipError_t e = launch_lookup((int)c->desc.storage, c->desc.pos_interp == FASTNERF_LINEAR,
+                               dev_cache(c), n, pts, dirs, sigma_u, beta, s);
+  if (e != hipSuccess) return hip_fail(e, "lookup");
+  return FASTNERF_OK;
+}
+
+extern "C" double fastnerf_model_bytes(double alpha, int64_t k, int64_t l, int32_t D,
+                                       double s_sigma, double s_uvw, double s_beta) {
+  const double k3 = (double)k * (double)k * (double)k;
+  return alpha * (((double)D * s_uvw + s_sigma) * k3) + (double)D * s_beta * (double)l * (double)l;
+}

@@ -1,0 +1,229 @@
+// Device-side data layout and lookups of the gfx950 FastNeRF renderer.
+//
+// Position cache: one record per voxel, {sigma, u[D][3]} in the storage format,
+// padded to a power-of-two stride (FP32 D=8: 100 B payload in 128 B, FP16 50 B
+// in 64 B, FP8 25 B in 32 B) so that a record never straddles a 128-byte line.
+// Records are stored brick-linear in 8^3 bricks (512 consecutive records per
+// brick, x fastest inside), so the rays of an 8x8 pixel tile, which sample
+// nearby voxels, touch few DRAM pages. Direction cache: FP32 [l][l][D].
+// Occupancy: one bit per brick of 2^oshift voxels, set when any voxel of the
+// brick (widened by one voxel for trilinear lookups) has a stored sigma > 0.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fnr {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kMaxD = 16;
+constexpr int kMaxCh = 1 + 3 * kMaxD;
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct DevCache {
+  const uint8_t *rec;
+  const float *beta;
+  const uint32_t *occ;   // nullptr: no empty-space skipping
+  const float *scales;   // 1 + 3D per-channel scales (FP8), ones otherwise
+  int k, D, l;
+  int nbl;               // layout bricks per axis
+  int nbo;               // occupancy bricks per axis
+  int oshift;            // log2 occupancy brick edge
+  int rec_shift;         // log2 record stride in bytes
+  int nchunk;            // 16-byte chunks holding the payload
+  float kf;              // k as float
+  float bmin[3], bmax[3], inv_h[3];
+  float th_scale, ph_scale;  // l/pi, l/(2 pi)
+  float bg[3];
+  int in_box, dir_linear;
+  int fmt;               // storage format of the records (0 FP32, 1 FP16, 2 BF16, 3 E4M3)
+};
+
+struct DevView {
+  float M[9];        // R K^-1: pixel (x+1/2, y+1/2, 1) -> world direction
+  float o[3];        // camera centre
+  float og[3];       // (o - bmin) * inv_h, the centre in grid units
+  float near_, far_;
+  int H, W, tiles_x, tile_begin;
+  int tile_offset;   // first tile of the view covered (serving steps cover tile ranges)
+  int scene;         // index into RenderArgs::caches (serving)
+  int N;             // samples per ray
+  float lim;         // ln(1/eps), +inf for eps = 0
+  float *out;        // float[H][W][4]
+};
+
+struct RenderArgs {
+  DevCache c;
+  DevView v0;               // used when views == nullptr
+  const DevView *views;     // batched launch: nviews views, tile_begin ascending
+  int nviews;
+  int total_tiles;
+  unsigned *counter;        // [0] next tile, [1] retired waves; self-resetting
+  unsigned nwaves;
+  const DevCache *caches;   // serving: per-scene caches (device), views[i].scene indexes it
+  const int *dyn_total;     // serving: {tile count, view count} of the step (device)
+};
+
+// ------------------------------------------------------------------ storage formats
+
+template <int FMT> struct Fmt;
+
+template <> struct Fmt<0> {  // FP32
+  static constexpr int bytes = 4;
+  __device__ static inline float get(const uint32_t *w, int j) { return __uint_as_float(w[j]); }
+};
+
+template <> struct Fmt<1> {  // FP16
+  static constexpr int bytes = 2;
+  __device__ static inline float get(const uint32_t *w, int j) {
+    uint32_t h = (w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu;
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+  }
+};
+
+template <> struct Fmt<2> {  // BF16
+  static constexpr int bytes = 2;
+  __device__ static inline float get(const uint32_t *w, int j) {
+    uint32_t h = (w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu;
+    return __uint_as_float(h << 16);
+  }
+};
+
+template <> struct Fmt<3> {  // OCP E4M3 code; the caller multiplies by the channel scale
+  static constexpr int bytes = 1;
+  // An E4M3 code e.mmm with bias 7 maps exactly onto binary16 with the same
+  // exponent/mantissa bits shifted into place (bias 15), scaled by 2^8; this
+  // holds for subnormal codes too. The NaN code is never stored (saturation).
+  __device__ static inline float get(const uint32_t *w, int j) {
+    uint32_t b = (w[j >> 2] >> ((j & 3) * 8)) & 0xFFu;
+    uint16_t h = (uint16_t)(((b & 0x80u) << 8) | ((b & 0x7Fu) << 7));
+    return (float)__builtin_bit_cast(_Float16, h) * 256.0f;
+  }
+};
+
+template <int FMT, int MAXD> struct RecWords {
+  static constexpr int nvals = 1 + 3 * MAXD;
+  static constexpr int bytes = nvals * Fmt<FMT>::bytes;
+  static constexpr int nchunk = (bytes + 15) / 16;
+  static constexpr int nwords = nchunk * 4;
+};
+
+// ------------------------------------------------------------------ addressing
+
+__device__ inline uint64_t record_offset(const DevCache &c, int x, int y, int z) {
+  uint32_t lb = ((uint32_t)(z >> 3) * (uint32_t)c.nbl + (uint32_t)(y >> 3)) * (uint32_t)c.nbl +
+                (uint32_t)(x >> 3);
+  uint32_t li = ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
+  return (((uint64_t)lb << 9) | li) << c.rec_shift;
+}
+
+__device__ inline bool occupied(const DevCache &c, int x, int y, int z) {
+  if (!c.occ) return true;
+  uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo + (uint32_t)(y >> c.oshift)) *
+                     (uint32_t)c.nbo +
+                 (uint32_t)(x >> c.oshift);
+  return (__ldg(c.occ + (bit >> 5)) >> (bit & 31)) & 1u;
+}
+
+template <int FMT, int MAXD>
+__device__ inline void load_record(const DevCache &c, uint64_t off, uint32_t *w) {
+  using RW = RecWords<FMT, MAXD>;
+  const u32x4 *p = reinterpret_cast<const u32x4 *>(c.rec + off);
+#pragma unroll
+  for (int q = 0; q < RW::nchunk; ++q) {
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (q < c.nchunk) v = __builtin_nontemporal_load(p + q);
+    w[4 * q + 0] = v.x;
+    w[4 * q + 1] = v.y;
+    w[4 * q + 2] = v.z;
+    w[4 * q + 3] = v.w;
+  }
+}
+
+// sigma of a loaded record (scaled)
+template <int FMT>
+__device__ inline float rec_sigma(const uint32_t *w, const float *sc) {
+  float s = Fmt<FMT>::get(w, 0);
+  if (FMT == 3) s *= sc[0];
+  return s;
+}
+
+// colour beta . (u, v, w) of a loaded record (Eq. 5); beta[d] = 0 for d >= D
+template <int FMT, int MAXD>
+__device__ inline void rec_colour(const uint32_t *w, const float *beta, const float *sc,
+                                  float &r, float &g, float &b) {
+  float cr = 0.f, cg = 0.f, cb = 0.f;
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) {
+    float ur = Fmt<FMT>::get(w, 1 + 3 * d + 0);
+    float ug = Fmt<FMT>::get(w, 1 + 3 * d + 1);
+    float ub = Fmt<FMT>::get(w, 1 + 3 * d + 2);
+    if (FMT == 3) {
+      ur *= sc[1 + 3 * d + 0];
+      ug *= sc[1 + 3 * d + 1];
+      ub *= sc[1 + 3 * d + 2];
+    }
+    cr = fmaf(beta[d], ur, cr);
+    cg = fmaf(beta[d], ug, cg);
+    cb = fmaf(beta[d], ub, cb);
+  }
+  r = cr;
+  g = cg;
+  b = cb;
+}
+
+// ------------------------------------------------------------------ direction cache
+
+__device__ inline void dir_cell_weights(const DevCache &c, float dx, float dy, float dz,
+                                        int cell[4], float wt[4]) {
+  float zc = fminf(fmaxf(dz, -1.0f), 1.0f);
+  float th = acosf(zc);
+  float ph = atan2f(dy, dx);
+  if (ph < 0.0f) ph += 6.28318530717958647692f;
+  const int l = c.l;
+  if (!c.dir_linear) {
+    int j = min((int)(th * c.th_scale), l - 1);
+    int m = (int)(ph * c.ph_scale);
+    if (m >= l) m -= l;
+    cell[0] = cell[1] = cell[2] = cell[3] = j * l + m;
+    wt[0] = 1.0f;
+    wt[1] = wt[2] = wt[3] = 0.0f;
+    return;
+  }
+  float gt = fmaf(th, c.th_scale, -0.5f), gp = fmaf(ph, c.ph_scale, -0.5f);
+  float ft = floorf(gt), fp = floorf(gp);
+  float a = gt - ft, b = gp - fp;
+  int j0 = (int)ft, m0 = (int)fp;
+  int ja = min(max(j0, 0), l - 1), jb = min(max(j0 + 1, 0), l - 1);
+  int ma = m0 < 0 ? m0 + l : (m0 >= l ? m0 - l : m0);
+  int mb = m0 + 1 >= l ? m0 + 1 - l : (m0 + 1 < 0 ? m0 + 1 + l : m0 + 1);
+  cell[0] = ja * l + ma;
+  cell[1] = ja * l + mb;
+  cell[2] = jb * l + ma;
+  cell[3] = jb * l + mb;
+  wt[0] = (1.0f - a) * (1.0f - b);
+  wt[1] = (1.0f - a) * b;
+  wt[2] = a * (1.0f - b);
+  wt[3] = a * b;
+}
+
+template <int MAXD>
+__device__ inline void dir_lookup(const DevCache &c, float dx, float dy, float dz,
+                                  float *beta) {
+  int cell[4];
+  float wt[4];
+  dir_cell_weights(c, dx, dy, dz, cell, wt);
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) beta[d] = 0.0f;
+  const int D = c.D;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float *bp = c.beta + (size_t)cell[q] * D;
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d)
+      if (d < D) beta[d] = fmaf(wt[q], __ldg(bp + d), beta[d]);
+  }
+}
+
+}  // namespace fnr

@@ -1,0 +1,22 @@
+// Launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include "fastnerf_device.h"
+
+namespace fnr {
+
+int render_occupancy(int fmt, bool lin, int D);
+int render_step_occupancy(bool lin, int D);
+hipError_t launch_render_step(bool lin, int D, const RenderArgs &a, int grid, hipStream_t s);
+hipError_t launch_render(int fmt, bool lin, const RenderArgs &a, int grid, hipStream_t s);
+hipError_t launch_absmax(const float *sigma, const float *u, int64_t nvox, int D, unsigned *amax,
+                         hipStream_t s);
+hipError_t launch_make_scales(const unsigned *amax, int nch, float *scales, hipStream_t s);
+hipError_t launch_pack(int fmt, const float *sigma, const float *u, int z0, int nz,
+                       const DevCache &c, hipStream_t s);
+hipError_t launch_occupancy(int fmt, const DevCache &c, int dilate, uint32_t *words,
+                            hipStream_t s);
+hipError_t launch_readback(int fmt, const DevCache &c, float *sigma, float *u, hipStream_t s);
+hipError_t launch_lookup(int fmt, bool lin, const DevCache &c, int n, const float *pts,
+                         const float *dirs, float *su, float *bo, hipStream_t s);
+
+}  // namespace fnr

@@ -1,0 +1,622 @@
+// gfx950 kernels of the FastNeRF cached renderer.
+//
+//   k_render      the hot path: rays of 8x8 pixel tiles (one tile per wave,
+//                 tiles taken from a persistent queue), empty-space skipping on
+//                 the brick bitgrid, record gathers, Eq. 5 colour, Eq. 1
+//                 compositing in optical depth with early termination.
+//   k_absmax      per-channel |max| for FP8 scales.
+//   k_pack        FP32 slab -> padded brick-linear records in the storage format.
+//   k_occupancy   brick bitgrid from the stored densities.
+//   k_readback    records -> FP32 arrays (test hook).
+//   k_lookup      the render kernel's own lookups at given points (test hook).
+#include "fastnerf_device.h"
+#include "fastnerf_kernels.h"
+
+namespace fnr {
+
+// ------------------------------------------------------------------ render
+
+// Samples in flight per lane between loads and compositing: enough record
+// bytes outstanding per wave to cover HBM latency without spilling VGPRs.
+template <int FMT, bool LIN> struct Batch {
+  static constexpr int value = LIN ? 1 : (FMT == 0 ? 2 : (FMT == 3 ? 4 : 4));
+};
+
+// Renders the rays of one 8x8 tile (one ray per lane) of view V with cache c.
+template <int FMT, int MAXD, bool LIN>
+__device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache &c,
+                                            const DevView &V, int lt, int lane) {
+  using RW = RecWords<FMT, MAXD>;
+  constexpr int B = Batch<FMT, LIN>::value;
+  const int W = V.W, H = V.H;
+  const int px = (lt % V.tiles_x) * 8 + (lane & 7);
+  const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
+  if (px >= W || py >= H) return;
+  float sc[FMT == 3 ? kMaxCh : 1];
+  if (FMT == 3) {
+#pragma unroll
+    for (int j = 0; j < (FMT == 3 ? kMaxCh : 1); ++j)
+      sc[j] = j < 1 + 3 * c.D ? c.scales[j] : 0.0f;
+  }
+  const int N = V.N;
+  const int k = c.k;
+  const float kf = c.kf;
+
+  // ray (reading: pixel centres, OpenCV axes, unit direction)
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  float dx = fmaf(V.M[0], fx, fmaf(V.M[1], fy, V.M[2]));
+  float dy = fmaf(V.M[3], fx, fmaf(V.M[4], fy, V.M[5]));
+  float dz = fmaf(V.M[6], fx, fmaf(V.M[7], fy, V.M[8]));
+  const float rn = 1.0f / sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+  dx *= rn;
+  dy *= rn;
+  dz *= rn;
+
+  // sample interval
+  float t0 = V.near_, t1 = V.far_;
+  if (c.in_box) {
+    const float o3[3] = {V.o[0], V.o[1], V.o[2]};
+    const float d3[3] = {dx, dy, dz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float lo = c.bmin[ax], hi = c.bmax[ax];
+      if (d3[ax] == 0.0f) {
+        if (o3[ax] < lo || o3[ax] > hi) t1 = -1.0f;
+      } else {
+        const float ta = (lo - o3[ax]) / d3[ax], tb = (hi - o3[ax]) / d3[ax];
+        t0 = fmaxf(t0, fminf(ta, tb));
+        t1 = fminf(t1, fmaxf(ta, tb));
+      }
+    }
+  }
+  float tau = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  if (t1 > t0) {
+    float beta[MAXD];
+    dir_lookup<MAXD>(c, dx, dy, dz, beta);
+    const float dt = (t1 - t0) / (float)N;
+    const float gdx = dx * c.inv_h[0], gdy = dy * c.inv_h[1], gdz = dz * c.inv_h[2];
+    const float ogx = V.og[0], ogy = V.og[1], ogz = V.og[2];
+    int i = 0;
+    bool alive = true;
+    while (alive) {
+      // find the next B samples that lie in occupied bricks
+      int vx[B], vy[B], vz[B];
+      float wx[B], wy[B], wz[B];
+      bool have[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        have[b] = false;
+        vx[b] = vy[b] = vz[b] = 0;
+        wx[b] = wy[b] = wz[b] = 0.0f;
+        while (i < N) {
+          const float t = fmaf((float)i + 0.5f, dt, t0);
+          ++i;
+          const float gx = fmaf(t, gdx, ogx), gy = fmaf(t, gdy, ogy), gz = fmaf(t, gdz, ogz);
+          if (!(gx >= 0.0f && gx <= kf && gy >= 0.0f && gy <= kf && gz >= 0.0f && gz <= kf))
+            continue;
+          const int x = min((int)gx, k - 1), y = min((int)gy, k - 1), z = min((int)gz, k - 1);
+          if (!occupied(c, x, y, z)) continue;
+          if (LIN) {
+            const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
+            const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
+            vx[b] = (int)fx0;
+            vy[b] = (int)fy0;
+            vz[b] = (int)fz0;
+            wx[b] = hx - fx0;
+            wy[b] = hy - fy0;
+            wz[b] = hz - fz0;
+          } else {
+            vx[b] = x;
+            vy[b] = y;
+            vz[b] = z;
+          }
+          have[b] = true;
+          break;
+        }
+      }
+      if (!LIN) {
+        uint32_t w[B][RW::nwords];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+          if (have[b]) load_record<FMT, MAXD>(c, record_offset(c, vx[b], vy[b], vz[b]), w[b]);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          if (!have[b] || !alive) continue;
+          if (tau > V.lim) {
+            alive = false;
+            continue;
+          }
+          const float s = rec_sigma<FMT>(w[b], sc);
+          float r, g, bl;
+          rec_colour<FMT, MAXD>(w[b], beta, sc, r, g, bl);
+          const float sd = s * dt;
+          const float wgt = expf(-tau) * -expm1f(-sd);
+          cr = fmaf(wgt, r, cr);
+          cg = fmaf(wgt, g, cg);
+          cb = fmaf(wgt, bl, cb);
+          tau += sd;
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          if (!have[b] || !alive) continue;
+          uint32_t w[8][RW::nwords];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int x = min(max(vx[b] + (q & 1), 0), k - 1);
+            const int y = min(max(vy[b] + ((q >> 1) & 1), 0), k - 1);
+            const int z = min(max(vz[b] + ((q >> 2) & 1), 0), k - 1);
+            load_record<FMT, MAXD>(c, record_offset(c, x, y, z), w[q]);
+          }
+          if (tau > V.lim) {
+            alive = false;
+            continue;
+          }
+          float s = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const float wq = ((q & 1) ? wx[b] : 1.0f - wx[b]) *
+                             (((q >> 1) & 1) ? wy[b] : 1.0f - wy[b]) *
+                             (((q >> 2) & 1) ? wz[b] : 1.0f - wz[b]);
+            float rq, gq, bq;
+            rec_colour<FMT, MAXD>(w[q], beta, sc, rq, gq, bq);
+            s = fmaf(wq, rec_sigma<FMT>(w[q], sc), s);
+            r = fmaf(wq, rq, r);
+            g = fmaf(wq, gq, g);
+            bl = fmaf(wq, bq, bl);
+          }
+          const float sd = s * dt;
+          const float wgt = expf(-tau) * -expm1f(-sd);
+          cr = fmaf(wgt, r, cr);
+          cg = fmaf(wgt, g, cg);
+          cb = fmaf(wgt, bl, cb);
+          tau += sd;
+        }
+      }
+      if (i >= N) alive = false;
+    }
+  }
+  const float T = expf(-tau);
+  float4 res;
+  res.x = fmaf(T, c.bg[0], cr);
+  res.y = fmaf(T, c.bg[1], cg);
+  res.z = fmaf(T, c.bg[2], cb);
+  res.w = -expm1f(-tau);
+  reinterpret_cast<float4 *>(V.out)[(size_t)py * W + px] = res;
+}
+
+// Takes the next tile from the persistent queue (uniform across the wave).
+__device__ __forceinline__ int next_tile(const RenderArgs &a, int lane) {
+  unsigned got = 0;
+  if (lane == 0) got = atomicAdd(a.counter, 1u);
+  return (int)__builtin_amdgcn_readfirstlane(got);
+}
+
+__device__ __forceinline__ int view_of_tile(const RenderArgs &a, int tile, int nviews) {
+  int lo = 0, hi = nviews - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.views[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The last wave to leave resets the queue for the next launch on this stream
+// (every wave has made its final fetch before it retires).
+__device__ __forceinline__ void retire(const RenderArgs &a, int lane) {
+  if (lane == 0) {
+    const unsigned done = atomicAdd(a.counter + 1, 1u);
+    if (done == a.nwaves - 1) {
+      atomicExch(a.counter, 0u);
+      atomicExch(a.counter + 1, 0u);
+    }
+  }
+}
+
+// One cache, one storage format: single views (inline descriptor) or batches.
+template <int FMT, int MAXD, bool LIN>
+__global__ void __launch_bounds__(kBlock) k_render(RenderArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (;;) {
+    const int tile = next_tile(a, lane);
+    if (tile >= a.total_tiles) break;
+    if (a.views) {
+      const DevView V = a.views[view_of_tile(a, tile, a.nviews)];
+      render_tile<FMT, MAXD, LIN>(a, a.c, V, tile - V.tile_begin + V.tile_offset, lane);
+    } else {
+      render_tile<FMT, MAXD, LIN>(a, a.c, a.v0, tile, lane);
+    }
+  }
+  retire(a, lane);
+}
+
+// Serving step: tile ranges of many views over several resident caches of any
+// storage format, in one launch; the step's size is read from device memory so
+// the launch can be replayed from a captured graph.
+template <int MAXD, bool LIN>
+__global__ void __launch_bounds__(kBlock) k_render_step(RenderArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int total = __builtin_amdgcn_readfirstlane(a.dyn_total[0]);
+  const int nviews = __builtin_amdgcn_readfirstlane(a.dyn_total[1]);
+  for (;;) {
+    const int tile = next_tile(a, lane);
+    if (tile >= total) break;
+    const DevView V = a.views[view_of_tile(a, tile, nviews)];
+    const DevCache c = a.caches[V.scene];
+    const int lt = tile - V.tile_begin + V.tile_offset;
+    switch (c.fmt) {
+      case 0: render_tile<0, MAXD, LIN>(a, c, V, lt, lane); break;
+      case 1: render_tile<1, MAXD, LIN>(a, c, V, lt, lane); break;
+      case 2: render_tile<2, MAXD, LIN>(a, c, V, lt, lane); break;
+      default: render_tile<3, MAXD, LIN>(a, c, V, lt, lane); break;
+    }
+  }
+  retire(a, lane);
+}
+
+// ------------------------------------------------------------------ cache build
+
+__device__ inline uint32_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return u >> 16;
+}
+
+// OCP E4M3 ("fn": bias 7, no infinities, 0x7F is NaN), round to nearest even,
+// saturating at 448.
+__device__ inline uint32_t f32_to_e4m3_sat(float y) {
+  const uint32_t sgn = (__float_as_uint(y) >> 24) & 0x80u;
+  const float a = fabsf(y);
+  if (!(a < 448.0f)) return sgn | (a != a ? 0x7Fu : 0x7Eu);
+  if (a < 0.015625f) {  // below 2^-6: multiples of 2^-9 (q = 8 carries into the first normal)
+    return sgn | (uint32_t)rintf(a * 512.0f);
+  }
+  const int e = (int)((__float_as_uint(a) >> 23) & 0xFF) - 127;  // 2^e <= a < 2^(e+1)
+  const uint32_t q = (uint32_t)rintf(ldexpf(a, 3 - e));          // 8..16, exact scaling
+  return sgn | ((uint32_t)(e + 7) << 3) + (q - 8u);
+}
+
+__global__ void k_absmax(const float *__restrict__ sigma, const float *__restrict__ u,
+                         int64_t nvox, int D, unsigned *__restrict__ amax) {
+  const int nch = 1 + 3 * D;
+  float m[kMaxCh];
+#pragma unroll
+  for (int j = 0; j < kMaxCh; ++j) m[j] = 0.0f;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    m[0] = fmaxf(m[0], fabsf(sigma[v]));
+#pragma unroll
+    for (int j = 1; j < kMaxCh; ++j)
+      if (j < nch) m[j] = fmaxf(m[j], fabsf(u[v * (nch - 1) + (j - 1)]));
+  }
+  __shared__ float red[kBlock / kWave][kMaxCh];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int j = 0; j < kMaxCh; ++j) {
+    if (j >= nch) break;
+    float x = m[j];
+    for (int off = kWave / 2; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off));
+    if (lane == 0) red[wv][j] = x;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nch) {
+    float x = 0.0f;
+    for (int q = 0; q < kBlock / kWave; ++q) x = fmaxf(x, red[q][threadIdx.x]);
+    atomicMax(amax + threadIdx.x, __float_as_uint(x));  // non-negative floats order as ints
+  }
+}
+
+__global__ void k_make_scales(const unsigned *amax, int nch, float *scales) {
+  const int j = threadIdx.x;
+  if (j < nch) {
+    const float a = __uint_as_float(amax[j]);
+    scales[j] = a > 0.0f ? __fdiv_rn(a, 448.0f) : 1.0f;
+  }
+}
+
+template <int FMT>
+__global__ void k_pack(const float *__restrict__ sigma, const float *__restrict__ u, int z0,
+                       int nz, DevCache c, float *scales_unused) {
+  (void)scales_unused;
+  const int k = c.k, D = c.D, nch = 1 + 3 * D;
+  const int64_t nvox = (int64_t)nz * k * k;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(v % k), y = (int)((v / k) % k), z = z0 + (int)(v / ((int64_t)k * k));
+    uint32_t w[(kMaxCh * 4 + 15) / 16 * 4];
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(w) / 4); ++q) w[q] = 0u;
+#pragma unroll
+    for (int j = 0; j < kMaxCh; ++j) {
+      if (j >= nch) break;
+      const float x32 = j == 0 ? sigma[v] : u[v * (nch - 1) + (j - 1)];
+      if (FMT == 0) {
+        w[j] = __float_as_uint(x32);
+      } else if (FMT == 1) {
+        const uint32_t h = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x32);
+        w[j >> 1] |= h << ((j & 1) * 16);
+      } else if (FMT == 2) {
+        w[j >> 1] |= f32_to_bf16_rne(x32) << ((j & 1) * 16);
+      } else {
+        const uint32_t q8 = f32_to_e4m3_sat(__fdiv_rn(x32, c.scales[j]));
+        w[j >> 2] |= q8 << ((j & 3) * 8);
+      }
+    }
+    u32x4 *dst = reinterpret_cast<u32x4 *>(const_cast<uint8_t *>(c.rec) +
+                                           record_offset(c, x, y, z));
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(w) / 16); ++q)
+      if (q < c.nchunk) dst[q] = u32x4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+  }
+}
+
+template <int FMT>
+__device__ inline float stored_sigma(const DevCache &c, int x, int y, int z) {
+  const uint32_t *p = reinterpret_cast<const uint32_t *>(c.rec + record_offset(c, x, y, z));
+  uint32_t w[1] = {p[0]};
+  return Fmt<FMT>::get(w, 0);  // sign and zero test only: the scale is positive
+}
+
+// one thread per brick; dilate = 1 widens the brick by one voxel on every side
+template <int FMT>
+__global__ void k_occupancy(DevCache c, int dilate, uint32_t *__restrict__ words) {
+  const int nb = c.nbo, e = 1 << c.oshift, k = c.k;
+  const int64_t nbr = (int64_t)nb * nb * nb;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nbr;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int bx = (int)(b % nb), by = (int)((b / nb) % nb), bz = (int)(b / ((int64_t)nb * nb));
+    const int x0 = max(bx * e - dilate, 0), x1 = min(bx * e + e + dilate, k);
+    const int y0 = max(by * e - dilate, 0), y1 = min(by * e + e + dilate, k);
+    const int z0 = max(bz * e - dilate, 0), z1 = min(bz * e + e + dilate, k);
+    bool any = false;
+    for (int z = z0; z < z1 && !any; ++z)
+      for (int y = y0; y < y1 && !any; ++y)
+        for (int x = x0; x < x1; ++x)
+          if (stored_sigma<FMT>(c, x, y, z) > 0.0f) {
+            any = true;
+            break;
+          }
+    if (any) atomicOr(words + (b >> 5), 1u << (b & 31));
+  }
+}
+
+template <int FMT, int MAXD>
+__global__ void k_readback(DevCache c, float *__restrict__ sigma, float *__restrict__ u) {
+  using RW = RecWords<FMT, MAXD>;
+  const int k = c.k, D = c.D;
+  const int64_t nvox = (int64_t)k * k * k;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(v % k), y = (int)((v / k) % k), z = (int)(v / ((int64_t)k * k));
+    uint32_t w[RW::nwords];
+    load_record<FMT, MAXD>(c, record_offset(c, x, y, z), w);
+#pragma unroll
+    for (int j = 0; j < 1 + 3 * MAXD; ++j) {
+      if (j >= 1 + 3 * D) break;
+      float val = Fmt<FMT>::get(w, j);
+      if (FMT == 3) val *= c.scales[j];
+      if (j == 0) sigma[v] = val; else u[v * 3 * D + (j - 1)] = val;
+    }
+  }
+}
+
+template <int FMT, int MAXD, bool LIN>
+__global__ void k_lookup(DevCache c, int n, const float *__restrict__ pts,
+                         const float *__restrict__ dirs, float *__restrict__ su,
+                         float *__restrict__ bo) {
+  using RW = RecWords<FMT, MAXD>;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int D = c.D, k = c.k;
+  float sc[kMaxCh];
+#pragma unroll
+  for (int j = 0; j < kMaxCh; ++j) sc[j] = (FMT == 3 && j < 1 + 3 * D) ? c.scales[j] : 1.0f;
+  if (dirs && bo) {
+    float beta[MAXD];
+    dir_lookup<MAXD>(c, dirs[3 * q], dirs[3 * q + 1], dirs[3 * q + 2], beta);
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d)
+      if (d < D) bo[(size_t)q * D + d] = beta[d];
+  }
+  if (!pts || !su) return;
+  float g[3];
+  bool inside = true;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    g[ax] = (pts[3 * q + ax] - c.bmin[ax]) * c.inv_h[ax];
+    inside = inside && g[ax] >= 0.0f && g[ax] <= c.kf;
+  }
+  float acc[kMaxCh];
+#pragma unroll
+  for (int j = 0; j < kMaxCh; ++j) acc[j] = 0.0f;
+  if (inside) {
+    for (int corner = 0; corner < (LIN ? 8 : 1); ++corner) {
+      int v[3];
+      float wt = 1.0f;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        if (LIN) {
+          const float h = g[ax] - 0.5f, f = floorf(h);
+          const int bit = (corner >> ax) & 1;
+          v[ax] = min(max((int)f + bit, 0), k - 1);
+          wt *= bit ? h - f : 1.0f - (h - f);
+        } else {
+          v[ax] = min((int)g[ax], k - 1);
+        }
+      }
+      uint32_t w[RW::nwords];
+      load_record<FMT, MAXD>(c, record_offset(c, v[0], v[1], v[2]), w);
+#pragma unroll
+      for (int j = 0; j < 1 + 3 * MAXD; ++j) acc[j] = fmaf(wt, Fmt<FMT>::get(w, j) * sc[j], acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 1 + 3 * MAXD; ++j)
+    if (j < 1 + 3 * D) su[(size_t)q * (1 + 3 * D) + j] = acc[j];
+}
+
+// ------------------------------------------------------------------ launchers
+
+namespace {
+
+template <int FMT, int MAXD, bool LIN>
+hipError_t launch_render_t(const RenderArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_render<FMT, MAXD, LIN>), dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int FMT, int MAXD, bool LIN>
+int occupancy_t() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render<FMT, MAXD, LIN>, kBlock, 0) !=
+      hipSuccess)
+    nb = 1;
+  return nb < 1 ? 1 : nb;
+}
+
+template <int FMT, bool LIN>
+hipError_t dispatch_maxd(int D, const RenderArgs *a, int grid, hipStream_t s, int *occ) {
+  if (D <= 4) return a ? launch_render_t<FMT, 4, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 4, LIN>(), hipSuccess);
+  if (D <= 8) return a ? launch_render_t<FMT, 8, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 8, LIN>(), hipSuccess);
+  return a ? launch_render_t<FMT, 16, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 16, LIN>(), hipSuccess);
+}
+
+template <int FMT>
+hipError_t dispatch_lin(bool lin, int D, const RenderArgs *a, int grid, hipStream_t s, int *occ) {
+  return lin ? dispatch_maxd<FMT, true>(D, a, grid, s, occ)
+             : dispatch_maxd<FMT, false>(D, a, grid, s, occ);
+}
+
+hipError_t dispatch(int fmt, bool lin, int D, const RenderArgs *a, int grid, hipStream_t s,
+                    int *occ) {
+  switch (fmt) {
+    case 0: return dispatch_lin<0>(lin, D, a, grid, s, occ);
+    case 1: return dispatch_lin<1>(lin, D, a, grid, s, occ);
+    case 2: return dispatch_lin<2>(lin, D, a, grid, s, occ);
+    default: return dispatch_lin<3>(lin, D, a, grid, s, occ);
+  }
+}
+
+template <int FMT>
+hipError_t launch_lookup_f(const DevCache &c, bool lin, int n, const float *pts,
+                           const float *dirs, float *su, float *bo, hipStream_t s) {
+  const int grid = (n + kBlock - 1) / kBlock;
+  if (c.D <= 4) {
+    if (lin) hipLaunchKernelGGL((k_lookup<FMT, 4, true>), dim3(grid), dim3(kBlock), 0, s, c, n, pts, dirs, su, bo);
+    else hipLaunchKernelGGL((k_lookup<FMT, 4, false>), dim3(grid), dim3(kBlock), 0, s, c, n, pts, dirs, su, bo);
+  } else if (c.D <= 8) {
+    if (lin) hipLaunchKernelGGL((k_lookup<FMT, 8, true>), dim3(grid), dim3(kBlock), 0, s, c, n, pts, dirs, su, bo);
+    else hipLaunchKernelGGL((k_lookup<FMT, 8, false>), dim3(grid), dim3(kBlock), 0, s, c, n, pts, dirs, su, bo);
+  } else {
+    if (lin) hipLaunchKernelGGL((k_lookup<FMT, 16, true>), dim3(grid), dim3(kBlock), 0, s, c, n, pts, dirs, su, bo);
+    else hipLaunchKernelGGL((k_lookup<FMT, 16, false>), dim3(grid), dim3(kBlock), 0, s, c, n, pts, dirs, su, bo);
+  }
+  return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_readback_f(const DevCache &c, float *sigma, float *u, hipStream_t s) {
+  const int grid = 2048;
+  if (c.D <= 4) hipLaunchKernelGGL((k_readback<FMT, 4>), dim3(grid), dim3(kBlock), 0, s, c, sigma, u);
+  else if (c.D <= 8) hipLaunchKernelGGL((k_readback<FMT, 8>), dim3(grid), dim3(kBlock), 0, s, c, sigma, u);
+  else hipLaunchKernelGGL((k_readback<FMT, 16>), dim3(grid), dim3(kBlock), 0, s, c, sigma, u);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_render_step(bool lin, int D, const RenderArgs &a, int grid, hipStream_t s) {
+  if (D <= 8) {
+    if (lin) hipLaunchKernelGGL((k_render_step<8, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_render_step<8, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  } else {
+    if (lin) hipLaunchKernelGGL((k_render_step<16, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_render_step<16, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+int render_step_occupancy(bool lin, int D) {
+  int nb = 0;
+  hipError_t e;
+  if (D <= 8)
+    e = lin ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<8, true>, kBlock, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<8, false>, kBlock, 0);
+  else
+    e = lin ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<16, true>, kBlock, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<16, false>, kBlock, 0);
+  return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+int render_occupancy(int fmt, bool lin, int D) {
+  int occ = 1;
+  (void)dispatch(fmt, lin, D, nullptr, 0, nullptr, &occ);
+  return occ;
+}
+
+hipError_t launch_render(int fmt, bool lin, const RenderArgs &a, int grid, hipStream_t s) {
+  return dispatch(fmt, lin, a.c.D, &a, grid, s, nullptr);
+}
+
+hipError_t launch_absmax(const float *sigma, const float *u, int64_t nvox, int D, unsigned *amax,
+                         hipStream_t s) {
+  int64_t blocks = (nvox + kBlock - 1) / kBlock;
+  const int grid = (int)(blocks < 1024 ? (blocks < 1 ? 1 : blocks) : 1024);
+  hipLaunchKernelGGL(k_absmax, dim3(grid), dim3(kBlock), 0, s, sigma, u, nvox, D, amax);
+  return hipGetLastError();
+}
+
+hipError_t launch_make_scales(const unsigned *amax, int nch, float *scales, hipStream_t s) {
+  hipLaunchKernelGGL(k_make_scales, dim3(1), dim3(64), 0, s, amax, nch, scales);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(int fmt, const float *sigma, const float *u, int z0, int nz,
+                       const DevCache &c, hipStream_t s) {
+  const int64_t nvox = (int64_t)nz * c.k * c.k;
+  int64_t blocks = (nvox + kBlock - 1) / kBlock;
+  const int grid = (int)(blocks < 65536 ? (blocks < 1 ? 1 : blocks) : 65536);
+  switch (fmt) {
+    case 0: hipLaunchKernelGGL(k_pack<0>, dim3(grid), dim3(kBlock), 0, s, sigma, u, z0, nz, c, nullptr); break;
+    case 1: hipLaunchKernelGGL(k_pack<1>, dim3(grid), dim3(kBlock), 0, s, sigma, u, z0, nz, c, nullptr); break;
+    case 2: hipLaunchKernelGGL(k_pack<2>, dim3(grid), dim3(kBlock), 0, s, sigma, u, z0, nz, c, nullptr); break;
+    default: hipLaunchKernelGGL(k_pack<3>, dim3(grid), dim3(kBlock), 0, s, sigma, u, z0, nz, c, nullptr); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_occupancy(int fmt, const DevCache &c, int dilate, uint32_t *words,
+                            hipStream_t s) {
+  const int64_t nbr = (int64_t)c.nbo * c.nbo * c.nbo;
+  int64_t blocks = (nbr + kBlock - 1) / kBlock;
+  const int grid = (int)(blocks < 65536 ? (blocks < 1 ? 1 : blocks) : 65536);
+  switch (fmt) {
+    case 0: hipLaunchKernelGGL(k_occupancy<0>, dim3(grid), dim3(kBlock), 0, s, c, dilate, words); break;
+    case 1: hipLaunchKernelGGL(k_occupancy<1>, dim3(grid), dim3(kBlock), 0, s, c, dilate, words); break;
+    case 2: hipLaunchKernelGGL(k_occupancy<2>, dim3(grid), dim3(kBlock), 0, s, c, dilate, words); break;
+    default: hipLaunchKernelGGL(k_occupancy<3>, dim3(grid), dim3(kBlock), 0, s, c, dilate, words); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_readback(int fmt, const DevCache &c, float *sigma, float *u, hipStream_t s) {
+  switch (fmt) {
+    case 0: return launch_readback_f<0>(c, sigma, u, s);
+    case 1: return launch_readback_f<1>(c, sigma, u, s);
+    case 2: return launch_readback_f<2>(c, sigma, u, s);
+    default: return launch_readback_f<3>(c, sigma, u, s);
+  }
+}
+
+hipError_t launch_lookup(int fmt, bool lin, const DevCache &c, int n, const float *pts,
+                         const float *dirs, float *su, float *bo, hipStream_t s) {
+  switch (fmt) {
+    case 0: return launch_lookup_f<0>(c, lin, n, pts, dirs, su, bo, s);
+    case 1: return launch_lookup_f<1>(c, lin, n, pts, dirs, su, bo, s);
+    case 2: return launch_lookup_f<2>(c, lin, n, pts, dirs, su, bo, s);
+    default: return launch_lookup_f<3>(c, lin, n, pts, dirs, su, bo, s);
+  }
+}
+
+}  // namespace fnr

@@ -1,0 +1,273 @@
+// Render server: the C ABI over the continuous-batching scheduler
+// (serve_core.h) with a GPU executor. Every step is one persistent launch of
+// k_render_step over the tile ranges of all scheduled requests, whatever their
+// scene or storage format; the launch and the copy of its descriptor table are
+// captured once into a HIP graph and replayed each step.
+#include <string.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "fastnerf.h"
+#include "fastnerf_internal.h"
+#include "fastnerf_kernels.h"
+#include "serve_core.h"
+
+using namespace fnr;
+namespace fs = fnr_serve;
+
+namespace {
+
+#define HIP_CHECK(call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+  } while (0)
+
+// Device image of a step: header {tiles, views} then the views.
+struct StepHeader {
+  int total;
+  int nviews;
+  int pad[2];
+};
+
+class GpuExecutor : public fs::Executor {
+ public:
+  GpuExecutor() {}
+  ~GpuExecutor() override { free_all(); }
+
+  fastnerf_status init(const std::vector<fastnerf_cache_s *> &scenes, int max_views,
+                       uint8_t *arena) {
+    scenes_ = scenes;
+    max_views_ = max_views;
+    arena_ = arena;
+    HIP_CHECK(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+    std::vector<DevCache> dc;
+    for (auto *c : scenes) dc.push_back(dev_cache(c));
+    HIP_CHECK(hipMalloc(&caches_, sizeof(DevCache) * dc.size()));
+    HIP_CHECK(hipMemcpy(caches_, dc.data(), sizeof(DevCache) * dc.size(), hipMemcpyHostToDevice));
+    table_bytes_ = sizeof(StepHeader) + sizeof(DevView) * (size_t)max_views;
+    int cus = 1;
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    cus_ = cus < 1 ? 1 : cus;
+    return FASTNERF_OK;
+  }
+
+  fs::Status run(const fs::Step &step, uint64_t) override {
+    // one launch per (interpolation, component-count) class present
+    std::map<int, std::vector<const fs::Segment *>> groups;
+    for (const auto &sg : step.segs) {
+      const fastnerf_cache_s *c = scenes_[sg.req->scene];
+      groups[group_key(c)].push_back(&sg);
+    }
+    for (auto &kv : groups) {
+      Group *g = nullptr;
+      if (group(kv.first, &g) != FASTNERF_OK) return fs::kDevice;
+      StepHeader *hh = reinterpret_cast<StepHeader *>(g->h_table);
+      DevView *hv = reinterpret_cast<DevView *>(g->h_table + sizeof(StepHeader));
+      int tb = 0, n = 0;
+      for (const fs::Segment *sg : kv.second) {
+        const fs::Request *r = sg->req;
+        fastnerf_cache_s *c = scenes_[r->scene];
+        make_view(c, r->K, r->c2w, r->H, r->W, r->near_, r->far_,
+                  reinterpret_cast<float *>(arena_ + r->off), tb, hv + n);
+        hv[n].tile_offset = sg->first;
+        hv[n].scene = r->scene;
+        hv[n].N = r->N;
+        hv[n].lim = eps_limit(r->eps);
+        tb += sg->count;
+        ++n;
+      }
+      hh->total = tb;
+      hh->nviews = n;
+      if (hipGraphLaunch(g->exec, stream_) != hipSuccess) return fs::kDevice;
+      for (const fs::Segment *sg : kv.second)
+        if (hipEventRecord(scenes_[sg->req->scene]->last_use, stream_) != hipSuccess)
+          return fs::kDevice;
+    }
+    // the pinned tables are rewritten next step: wait for this one
+    return hipStreamSynchronize(stream_) == hipSuccess ? fs::kOk : fs::kDevice;
+  }
+
+ private:
+  struct Group {
+    uint8_t *h_table = nullptr;  // pinned
+    uint8_t *d_table = nullptr;
+    unsigned *counter = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+
+  static int group_key(const fastnerf_cache_s *c) {
+    return (c->desc.pos_interp == FASTNERF_LINEAR ? 2 : 0) + (c->desc.D <= 8 ? 0 : 1);
+  }
+
+  fastnerf_status group(int key, Group **out) {
+    auto it = groups_.find(key);
+    if (it != groups_.end()) {
+      *out = it->second.get();
+      return FASTNERF_OK;
+    }
+    std::unique_ptr<Group> g(new Group());
+    HIP_CHECK(hipHostMalloc(&g->h_table, table_bytes_, hipHostMallocDefault));
+    memset(g->h_table, 0, table_bytes_);
+    HIP_CHECK(hipMalloc(&g->d_table, table_bytes_));
+    HIP_CHECK(hipMalloc(&g->counter, 2 * sizeof(unsigned)));
+    HIP_CHECK(hipMemset(g->counter, 0, 2 * sizeof(unsigned)));
+    const bool lin = key & 2;
+    const int D = (key & 1) ? 16 : 8;
+    const int grid = cus_ * render_step_occupancy(lin, D);
+    RenderArgs a;
+    memset(&a, 0, sizeof a);
+    a.views = reinterpret_cast<const DevView *>(g->d_table + sizeof(StepHeader));
+    a.dyn_total = reinterpret_cast<const int *>(g->d_table);
+    a.caches = caches_;
+    a.counter = g->counter;
+    a.nwaves = (unsigned)grid * (kBlock / kWave);
+    HIP_CHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipMemcpyAsync(g->d_table, g->h_table, table_bytes_, hipMemcpyHostToDevice,
+                                  stream_);
+    if (e == hipSuccess) e = launch_render_step(lin, D, a, grid, stream_);
+    hipError_t e2 = hipStreamEndCapture(stream_, &g->graph);
+    if (e != hipSuccess) return hip_fail(e, "step capture");
+    if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+    HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    *out = g.get();
+    groups_[key] = std::move(g);
+    return FASTNERF_OK;
+  }
+
+  void free_all() {
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    for (auto &kv : groups_) {
+      Group *g = kv.second.get();
+      if (g->exec) (void)hipGraphExecDestroy(g->exec);
+      if (g->graph) (void)hipGraphDestroy(g->graph);
+      if (g->h_table) (void)hipHostFree(g->h_table);
+      if (g->d_table) (void)hipFree(g->d_table);
+      if (g->counter) (void)hipFree(g->counter);
+    }
+    groups_.clear();
+    if (caches_) (void)hipFree(caches_);
+    caches_ = nullptr;
+    if (stream_) (void)hipStreamDestroy(stream_);
+    stream_ = nullptr;
+  }
+
+  std::vector<fastnerf_cache_s *> scenes_;
+  int max_views_ = 0, cus_ = 1;
+  size_t table_bytes_ = 0;
+  uint8_t *arena_ = nullptr;
+  DevCache *caches_ = nullptr;
+  hipStream_t stream_ = nullptr;
+  std::map<int, std::unique_ptr<Group>> groups_;
+};
+
+}  // namespace
+
+struct fastnerf_server_s {
+  std::vector<fastnerf_cache_s *> scenes;
+  uint8_t *arena = nullptr;
+  GpuExecutor exec;
+  std::unique_ptr<fs::Core> core;
+};
+
+static fastnerf_status from_core(fs::Status s, const char *what) {
+  if (s == fs::kOk) return FASTNERF_OK;
+  return fail((fastnerf_status)s, "%s", what);
+}
+
+extern "C" fastnerf_status fastnerf_server_create(const fastnerf_cache *scenes, int32_t nscenes,
+                                                  uint64_t arena_bytes, int32_t max_inflight,
+                                                  fastnerf_server *out) {
+  if (!scenes || nscenes < 1 || !out) return fail(FASTNERF_EINVAL, "no scenes or null out");
+  if (max_inflight < 1 || max_inflight > 4096)
+    return fail(FASTNERF_EINVAL, "max_inflight = %d outside [1, 4096]", max_inflight);
+  if (arena_bytes < 256) return fail(FASTNERF_EINVAL, "arena too small");
+  for (int i = 0; i < nscenes; ++i)
+    if (!scenes[i] || !scenes[i]->finalized)
+      return fail(FASTNERF_EINVAL, "scene %d is null or not finalized", i);
+  std::unique_ptr<fastnerf_server_s> s(new (std::nothrow) fastnerf_server_s());
+  if (!s) return fail(FASTNERF_ENOMEM, "host allocation");
+  s->scenes.assign(scenes, scenes + nscenes);
+  hipError_t e = hipMalloc(&s->arena, arena_bytes);
+  if (e != hipSuccess) return hip_fail(e, "arena");
+  fastnerf_status st = s->exec.init(s->scenes, max_inflight, s->arena);
+  if (st != FASTNERF_OK) {
+    (void)hipFree(s->arena);
+    return st;
+  }
+  fs::Config cfg;
+  cfg.arena_bytes = arena_bytes;
+  cfg.max_inflight = max_inflight;
+  s->core.reset(new fs::Core(cfg, &s->exec));
+  *out = s.release();
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_serve_submit(fastnerf_server s, int32_t scene,
+                                                 const float K[9], const float c2w[12],
+                                                 int32_t H, int32_t W, float near_, float far_,
+                                                 int32_t N, float eps, uint64_t *ticket) {
+  if (!s || !ticket) return fail(FASTNERF_EINVAL, "null server or ticket");
+  if (scene < 0 || scene >= (int)s->scenes.size())
+    return fail(FASTNERF_EINVAL, "scene %d out of range", scene);
+  static const float dummy = 0.0f;
+  fastnerf_status st = check_view(K, c2w, H, W, near_, far_, &dummy);
+  if (st == FASTNERF_OK) st = check_render_params(N, eps);
+  if (st != FASTNERF_OK) return st;
+  std::unique_ptr<fs::Request> r(new fs::Request());
+  r->scene = scene;
+  memcpy(r->K, K, sizeof r->K);
+  memcpy(r->c2w, c2w, sizeof r->c2w);
+  r->H = H;
+  r->W = W;
+  r->near_ = near_;
+  r->far_ = far_;
+  r->N = N;
+  r->eps = eps;
+  r->bytes = (uint64_t)H * W * 4 * sizeof(float);
+  return from_core(s->core->submit(std::move(r), ticket), "submit");
+}
+
+extern "C" fastnerf_status fastnerf_serve_wait(fastnerf_server s, uint64_t ticket,
+                                               int64_t timeout_us, const float **out_device,
+                                               double *latency_ms) {
+  if (!s) return fail(FASTNERF_EINVAL, "null server");
+  uint64_t off = 0;
+  fs::Status r = s->core->wait(ticket, timeout_us, &off, latency_ms);
+  if (r == fs::kOk && out_device) *out_device = reinterpret_cast<const float *>(s->arena + off);
+  return from_core(r, "wait");
+}
+
+extern "C" fastnerf_status fastnerf_serve_release(fastnerf_server s, uint64_t ticket) {
+  if (!s) return fail(FASTNERF_EINVAL, "null server");
+  return from_core(s->core->release(ticket), "release");
+}
+
+extern "C" fastnerf_status fastnerf_serve_cancel(fastnerf_server s, uint64_t ticket) {
+  if (!s) return fail(FASTNERF_EINVAL, "null server");
+  return from_core(s->core->cancel(ticket), "cancel");
+}
+
+extern "C" fastnerf_status fastnerf_server_stats(fastnerf_server s, uint64_t *steps,
+                                                 uint64_t *completed, uint64_t *max_batch) {
+  if (!s) return fail(FASTNERF_EINVAL, "null server");
+  s->core->stats(steps, completed, max_batch);
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_server_destroy(fastnerf_server s) {
+  if (!s) return fail(FASTNERF_EINVAL, "null server");
+  s->core->shutdown();
+  s->core.reset();
+  s->exec.~GpuExecutor();
+  new (&s->exec) GpuExecutor();
+  if (s->arena) (void)hipFree(s->arena);
+  delete s;
+  return FASTNERF_OK;
+}

@@ -130,13 +130,13 @@ def _bisect_factor(p: SceneParams, spec: SceneSpec, rng) -> float:
     k, m = spec.k, spec.margin
     lo_b, hi_b = spec.bbox
     h = (hi_b - lo_b) / k
-    idx = rng.integers(0, k, (1 << 17, 3))
+    idx = rng.integers(0, k, (1 << 16, 3))
     x = lo_b + (idx + 0.5) * h
     keep = np.all((idx >= m) & (idx < k - m), axis=1)
     target = 0.5 * (spec.occupancy[0] + spec.occupancy[1])
     shell = np.arange(len(p.dens)) >= spec.n_ellipsoids
     a, b = 0.2, 3.0
-    for _ in range(24):
+    for _ in range(20):
         f = 0.5 * (a + b)
         axes = p.axes * f
         w = np.zeros(len(p.dens))
@@ -357,3 +357,28 @@ def brick_sparse(p: SceneParams, sb: int, device="cpu", on_slab=None):
     ss = np.concatenate(sl) if sl else np.zeros((0, sb ** 3), np.float32)
     us = np.concatenate(ul) if ul else np.zeros((0, sb ** 3, D, 3), np.float32)
     return slot, ss, us
+
+
+# --------------------------------------------------------------- named workloads
+
+def plain_scene_spec():
+    """Plain-method scene: k=128, D=8, l=64, 6 ellipsoids, seed 0."""
+    return SceneSpec(k=128, D=8, l=64, n_ellipsoids=6, seed=0)
+
+
+def plain_view():
+    """One 200x200 view at radius 3 (az 0.7, el 0.4 rad), samples in [2, 4]."""
+    return orbit_view(3.0, 0.7, 0.4, 200, 200, 2.0, 4.0)
+
+
+def paper_scene_spec(k=768, seed=1):
+    """Paper-scale scene: D=8, l=384, 28 ellipsoids and 12 thin shells scaled to
+    7.5-8.5% voxel occupancy."""
+    return SceneSpec(k=k, D=8, l=384, n_ellipsoids=28, n_shells=12, seed=seed,
+                     occupancy=(0.075, 0.085))
+
+
+def paper_orbit(n=40, W=800, H=800, r=4.0, el=0.5):
+    """n views on an orbit at radius r, elevation el, az = 2 pi v / n + 0.1,
+    focal 1.2 W; samples span [0, 100] clipped to the box."""
+    return [orbit_view(r, 2 * math.pi * v / n + 0.1, el, W, H, 0.0, 100.0) for v in range(n)]

@@ -1,0 +1,75 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+rejects bad arguments before touching a device (no GPU needed)."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fastnerf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fastnerf_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2103_10380_amd import _lib
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2103_10380_amd import _lib
+    assert sorted(_lib.SYMBOLS) == _declared()
+
+
+def test_model_bytes_worked_example(L):
+    """Supplementary S4 (second printing): k = l = 1024, D = 8, half floats."""
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "cache_size_s4.json")))
+    from paper_2103_10380_amd import model_bytes
+    # s_uvw = one (u, v, w) triple of half floats, s_sigma = s_beta = one half float
+    pos = model_bytes(1.0, g["k"], g["l"], g["D"], 2, 6, 2) - model_bytes(0.0, g["k"], g["l"],
+                                                                          g["D"], 2, 6, 2)
+    assert pos == g["position_bytes_per_unit_alpha"]
+    assert model_bytes(0.0, g["k"], g["l"], g["D"], 2, 6, 2) == g["direction_bytes"]
+    assert model_bytes(0.01, 1024, 1024, 8, 2, 6, 2) == pytest.approx(
+        0.01 * g["position_bytes_per_unit_alpha"] + g["direction_bytes"])
+
+
+def test_bad_descriptors_rejected_without_device(L):
+    import paper_2103_10380_amd as fn
+    from paper_2103_10380_amd._lib import Desc
+    h = ctypes.c_void_p()
+    for kw in (dict(k=0), dict(D=0), dict(D=17), dict(l=0), dict(brick=3), dict(brick=16, k=24),
+               dict(storage=7)):
+        args = dict(k=kw.pop("k", 32), D=kw.pop("D", 8), l=kw.pop("l", 8))
+        d = fn.make_desc(args["k"], args["D"], args["l"], **kw)
+        st = L.fastnerf_cache_create_empty(ctypes.byref(d), ctypes.c_void_p(1), None,
+                                           ctypes.byref(h))
+        assert st == -1, kw
+        assert L.fastnerf_last_error()
+    st = L.fastnerf_cache_create_empty(None, None, None, ctypes.byref(h))
+    assert st == -1
+    d = Desc()
+    assert L.fastnerf_cache_create_empty(ctypes.byref(d), None, None, ctypes.byref(h)) == -1
+
+
+def test_null_handles_rejected(L):
+    K = (ctypes.c_float * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    C = (ctypes.c_float * 12)()
+    assert L.fastnerf_render(None, K, C, 8, 8, 1.0, 2.0, 8, 0.0, ctypes.c_void_p(1), None) == -1
+    assert L.fastnerf_cache_destroy(None) == -1
+    assert L.fastnerf_cache_finalize(None, None) == -1
+    v = ctypes.c_uint64()
+    assert L.fastnerf_cache_bytes(None, ctypes.byref(v)) == -1
