@@ -42,6 +42,15 @@
  *      either neighbour, and a stop point within tau_band of ln(1/eps) may be
  *      taken or not: all such variants are admissible results (the FP32 kernel
  *      cannot resolve them), and they are enumerated.
+ *   R13b when the sample spacing is commensurate with the grid (k/N voxels per
+ *      sample along an axis the ray crosses from face to face, e.g. k = 768,
+ *      N = 192) every sample lies on a voxel face, and the nearest voxel is
+ *      decided by rounding. The decision is then taken in FP32, the kernel's
+ *      precision: with g0 = float((o + t0 d - bmin) h^-1), e = float(d h^-1),
+ *      dt = float((t1 - t0)/N) and h^-1 = float(k/(bmax - bmin)), sample i has
+ *      g = fmaf(float(i + 1/2) * dt, e, g0) per axis, is inside when
+ *      0 <= g <= k and takes voxel min(floor(g), k - 1). Only this integer is
+ *      taken from FP32; positions, values and compositing stay FP64.
  *   R17 the transmittance sum of Eq. 1 runs over the samples before i.
  */
 #include "fastnerf_oracle.h"
@@ -390,9 +399,15 @@ static void composite(const orc_scene *s, const orc_view *v, const orc_tol *tol,
   double lim = v->eps > 0.0 ? log(1.0 / v->eps) : INFINITY;
   double band = tol ? tol->tau_band : 0.0;
   int primary_done = 0;
+  int changed = 1; /* (C, tau) moved since the last admissible stop was recorded */
   double uu[48];
   for (int i = 0; i < w->n; i++) {
-    if (tau > lim - band) cand_push(cl, C, tau, s->bg);
+    /* stopping before an empty sample gives the same result as stopping after
+       it, so only distinct stop points are recorded */
+    if (tau > lim - band && changed) {
+      cand_push(cl, C, tau, s->bg);
+      changed = 0;
+    }
     if (!primary_done && tau > lim) {
       double T = exp(-tau);
       for (int c = 0; c < 3; c++) prim[c] = C[c] + T * s->bg[c];
@@ -422,8 +437,9 @@ static void composite(const orc_scene *s, const orc_view *v, const orc_tol *tol,
     double T = exp(-tau);
     for (int c = 0; c < 3; c++) C[c] += T * alpha * col[c];
     tau += sig * delta;
+    if (sig != 0.0) changed = 1;
   }
-  cand_push(cl, C, tau, s->bg);
+  if (changed) cand_push(cl, C, tau, s->bg);
   if (!primary_done) {
     double T = exp(-tau);
     for (int c = 0; c < 3; c++) prim[c] = C[c] + T * s->bg[c];
@@ -447,6 +463,19 @@ static int place_samples(const orc_scene *s, const orc_view *v, const orc_tol *t
       w->p[i][ax] = o[ax] + t * d[ax];
       g[ax] = grid_coord(s, ax, w->p[i][ax]);
       w->c[i][ax] = nn_coord(g[ax], k);
+    }
+    if (!s->pos_linear && tol && tol->fp32_voxels) {
+      for (int ax = 0; ax < 3; ax++) {
+        float ih = (float)((double)k / (s->bmax[ax] - s->bmin[ax]));
+        float g0 = (float)((fma(t0, d[ax], o[ax]) - s->bmin[ax]) * (double)ih);
+        float e = (float)(d[ax] * (double)ih);
+        float dt = (float)delta;
+        float gf = fmaf(((float)i + 0.5f) * dt, e, g0);
+        w->c[i][ax] = (gf >= 0.0f && gf <= (float)k) ? (int)fminf(floorf(gf), (float)(k - 1)) : -1;
+      }
+      if (w->c[i][0] < 0 || w->c[i][1] < 0 || w->c[i][2] < 0)
+        w->c[i][0] = w->c[i][1] = w->c[i][2] = -1;
+      continue;
     }
     if (s->pos_linear || !tol || tol->gamma <= 0.0) continue;
     int amb = 0, alts[3], has[3];

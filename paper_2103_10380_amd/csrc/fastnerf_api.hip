@@ -151,7 +151,7 @@ int persistent_grid(const fastnerf_cache_s *c, int total_tiles) {
   return need < blocks ? (need < 1 ? 1 : need) : blocks;
 }
 
-// View descriptor from K and c2w. R K^-1 is formed in double and rounded once.
+// View descriptor from K and c2w; R K^-1 is formed and kept in double.
 void make_view(const fastnerf_cache_s *c, const float K[9], const float c2w[12], int H, int W,
                float near_, float far_, float *out, int tile_begin, DevView *v) {
   const double a = K[0], b = K[1], cc = K[2], d = K[3], e = K[4], f = K[5], g = K[6], h = K[7],
@@ -165,13 +165,10 @@ void make_view(const fastnerf_cache_s *c, const float K[9], const float c2w[12],
     for (int col = 0; col < 3; ++col) {
       double s = 0.0;
       for (int q = 0; q < 3; ++q) s += (double)c2w[4 * r + q] * Ki[3 * q + col];
-      v->M[3 * r + col] = (float)s;
+      v->M[3 * r + col] = s;
     }
-  for (int r = 0; r < 3; ++r) {
-    v->o[r] = c2w[4 * r + 3];
-    v->og[r] = (float)(((double)c2w[4 * r + 3] - (double)c->desc.bbox_min[r]) * c->desc.k /
-                       ((double)c->desc.bbox_max[r] - (double)c->desc.bbox_min[r]));
-  }
+  for (int r = 0; r < 3; ++r) v->o[r] = c2w[4 * r + 3];
+  (void)c;
   v->near_ = near_;
   v->far_ = far_;
   v->H = H;

@@ -41,9 +41,8 @@ struct DevCache {
 };
 
 struct DevView {
-  float M[9];        // R K^-1: pixel (x+1/2, y+1/2, 1) -> world direction
-  float o[3];        // camera centre
-  float og[3];       // (o - bmin) * inv_h, the centre in grid units
+  double M[9];       // R K^-1: pixel (x+1/2, y+1/2, 1) -> world direction
+  double o[3];       // camera centre
   float near_, far_;
   int H, W, tiles_x, tile_begin;
   int tile_offset;   // first tile of the view covered (serving steps cover tile ranges)

@@ -18,6 +18,9 @@ namespace fnr {
 
 // Samples in flight per lane between loads and compositing: enough record
 // bytes outstanding per wave to cover HBM latency without spilling VGPRs.
+// Samples whose occupancy bits are fetched together.
+constexpr int kWin = 8;
+
 template <int FMT, bool LIN> struct Batch {
   static constexpr int value = LIN ? 1 : (FMT == 0 ? 2 : (FMT == 3 ? 4 : 4));
 };
@@ -42,137 +45,165 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
   const int k = c.k;
   const float kf = c.kf;
 
-  // ray (reading: pixel centres, OpenCV axes, unit direction)
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  float dx = fmaf(V.M[0], fx, fmaf(V.M[1], fy, V.M[2]));
-  float dy = fmaf(V.M[3], fx, fmaf(V.M[4], fy, V.M[5]));
-  float dz = fmaf(V.M[6], fx, fmaf(V.M[7], fy, V.M[8]));
-  const float rn = 1.0f / sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-  dx *= rn;
-  dy *= rn;
-  dz *= rn;
+  // Ray set-up, once per ray, in FP64: the direction's small components and
+  // the box-entry distance are sensitive to rounding (near-grazing rays), and
+  // every sample position depends on them. Reading: pixel centres, OpenCV
+  // axes, unit direction.
+  const double qx = (double)px + 0.5, qy = (double)py + 0.5;
+  double ddx = fma(V.M[0], qx, fma(V.M[1], qy, V.M[2]));
+  double ddy = fma(V.M[3], qx, fma(V.M[4], qy, V.M[5]));
+  double ddz = fma(V.M[6], qx, fma(V.M[7], qy, V.M[8]));
+  const double rn = 1.0 / sqrt(fma(ddx, ddx, fma(ddy, ddy, ddz * ddz)));
+  ddx *= rn;
+  ddy *= rn;
+  ddz *= rn;
 
   // sample interval
-  float t0 = V.near_, t1 = V.far_;
+  double t0 = V.near_, t1 = V.far_;
   if (c.in_box) {
-    const float o3[3] = {V.o[0], V.o[1], V.o[2]};
-    const float d3[3] = {dx, dy, dz};
+    const double d3[3] = {ddx, ddy, ddz};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const float lo = c.bmin[ax], hi = c.bmax[ax];
-      if (d3[ax] == 0.0f) {
-        if (o3[ax] < lo || o3[ax] > hi) t1 = -1.0f;
+      const double lo = c.bmin[ax], hi = c.bmax[ax];
+      if (d3[ax] == 0.0) {
+        if (V.o[ax] < lo || V.o[ax] > hi) t1 = -1.0;
       } else {
-        const float ta = (lo - o3[ax]) / d3[ax], tb = (hi - o3[ax]) / d3[ax];
-        t0 = fmaxf(t0, fminf(ta, tb));
-        t1 = fminf(t1, fmaxf(ta, tb));
+        const double ta = (lo - V.o[ax]) / d3[ax], tb = (hi - V.o[ax]) / d3[ax];
+        t0 = fmax(t0, fmin(ta, tb));
+        t1 = fmin(t1, fmax(ta, tb));
       }
     }
   }
   float tau = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
   if (t1 > t0) {
     float beta[MAXD];
-    dir_lookup<MAXD>(c, dx, dy, dz, beta);
-    const float dt = (t1 - t0) / (float)N;
-    const float gdx = dx * c.inv_h[0], gdy = dy * c.inv_h[1], gdz = dz * c.inv_h[2];
-    const float ogx = V.og[0], ogy = V.og[1], ogz = V.og[2];
+    dir_lookup<MAXD>(c, (float)ddx, (float)ddy, (float)ddz, beta);
+    const float dt = (float)((t1 - t0) / (double)N);
+    // grid coordinates of the interval start and the per-distance step;
+    // sample i sits at distance (i + 1/2) dt past the start
+    const float ogx = (float)((fma(t0, ddx, V.o[0]) - c.bmin[0]) * c.inv_h[0]);
+    const float ogy = (float)((fma(t0, ddy, V.o[1]) - c.bmin[1]) * c.inv_h[1]);
+    const float ogz = (float)((fma(t0, ddz, V.o[2]) - c.bmin[2]) * c.inv_h[2]);
+    const float gdx = (float)(ddx * c.inv_h[0]), gdy = (float)(ddy * c.inv_h[1]),
+                gdz = (float)(ddz * c.inv_h[2]);
+    // Samples are taken in windows of kWin: the occupancy bits of a window are
+    // fetched with independent loads and one wait, then its occupied samples
+    // are gathered and composited in order, B records in flight at a time.
+    const bool skip = c.occ != nullptr;
     int i = 0;
     bool alive = true;
     while (alive) {
-      // find the next B samples that lie in occupied bricks
-      int vx[B], vy[B], vz[B];
-      float wx[B], wy[B], wz[B];
-      bool have[B];
+      uint32_t mask = 0u;
+      {
+        uint32_t word[kWin], bitpos[kWin];
+        bool in[kWin];
 #pragma unroll
-      for (int b = 0; b < B; ++b) {
-        have[b] = false;
-        vx[b] = vy[b] = vz[b] = 0;
-        wx[b] = wy[b] = wz[b] = 0.0f;
-        while (i < N) {
-          const float t = fmaf((float)i + 0.5f, dt, t0);
-          ++i;
+        for (int j = 0; j < kWin; ++j) {
+          const float t = ((float)(i + j) + 0.5f) * dt;
           const float gx = fmaf(t, gdx, ogx), gy = fmaf(t, gdy, ogy), gz = fmaf(t, gdz, ogz);
-          if (!(gx >= 0.0f && gx <= kf && gy >= 0.0f && gy <= kf && gz >= 0.0f && gz <= kf))
-            continue;
-          const int x = min((int)gx, k - 1), y = min((int)gy, k - 1), z = min((int)gz, k - 1);
-          if (!occupied(c, x, y, z)) continue;
-          if (LIN) {
-            const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
-            const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
-            vx[b] = (int)fx0;
-            vy[b] = (int)fy0;
-            vz[b] = (int)fz0;
-            wx[b] = hx - fx0;
-            wy[b] = hy - fy0;
-            wz[b] = hz - fz0;
-          } else {
-            vx[b] = x;
-            vy[b] = y;
-            vz[b] = z;
+          in[j] = (i + j < N) && gx >= 0.0f && gx <= kf && gy >= 0.0f && gy <= kf &&
+                  gz >= 0.0f && gz <= kf;
+          word[j] = ~0u;
+          bitpos[j] = 0u;
+          if (skip) {  // clamped voxel: always a valid address, even when not inside
+            const int x = min(max((int)gx, 0), k - 1), y = min(max((int)gy, 0), k - 1),
+                      z = min(max((int)gz, 0), k - 1);
+            const uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo +
+                                  (uint32_t)(y >> c.oshift)) * (uint32_t)c.nbo +
+                                 (uint32_t)(x >> c.oshift);
+            word[j] = __ldg(c.occ + (bit >> 5));
+            bitpos[j] = bit & 31u;
           }
-          have[b] = true;
-          break;
         }
-      }
-      if (!LIN) {
-        uint32_t w[B][RW::nwords];
 #pragma unroll
-        for (int b = 0; b < B; ++b)
-          if (have[b]) load_record<FMT, MAXD>(c, record_offset(c, vx[b], vy[b], vz[b]), w[b]);
+        for (int j = 0; j < kWin; ++j)
+          mask |= (uint32_t)(in[j] && ((word[j] >> bitpos[j]) & 1u)) << j;
+      }
+      while (mask != 0u && alive) {
+        int vx[B], vy[B], vz[B];
+        float wx[B], wy[B], wz[B];
+        bool have[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-          if (!have[b] || !alive) continue;
-          if (tau > V.lim) {
-            alive = false;
-            continue;
+          have[b] = mask != 0u;
+          vx[b] = vy[b] = vz[b] = 0;
+          wx[b] = wy[b] = wz[b] = 0.0f;
+          if (have[b]) {
+            const int j = __builtin_ctz(mask);
+            mask &= mask - 1u;
+            const float t = ((float)(i + j) + 0.5f) * dt;
+            const float gx = fmaf(t, gdx, ogx), gy = fmaf(t, gdy, ogy), gz = fmaf(t, gdz, ogz);
+            if (LIN) {
+              const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
+              const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
+              vx[b] = (int)fx0;
+              vy[b] = (int)fy0;
+              vz[b] = (int)fz0;
+              wx[b] = hx - fx0;
+              wy[b] = hy - fy0;
+              wz[b] = hz - fz0;
+            } else {
+              vx[b] = min((int)gx, k - 1);
+              vy[b] = min((int)gy, k - 1);
+              vz[b] = min((int)gz, k - 1);
+            }
           }
-          const float s = rec_sigma<FMT>(w[b], sc);
-          float r, g, bl;
-          rec_colour<FMT, MAXD>(w[b], beta, sc, r, g, bl);
-          const float sd = s * dt;
-          const float wgt = expf(-tau) * -expm1f(-sd);
-          cr = fmaf(wgt, r, cr);
-          cg = fmaf(wgt, g, cg);
-          cb = fmaf(wgt, bl, cb);
-          tau += sd;
         }
-      } else {
+        if (!LIN) {
+          uint32_t w[B][RW::nwords];
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-          if (!have[b] || !alive) continue;
-          uint32_t w[8][RW::nwords];
+          for (int b = 0; b < B; ++b)
+            if (have[b]) load_record<FMT, MAXD>(c, record_offset(c, vx[b], vy[b], vz[b]), w[b]);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int x = min(max(vx[b] + (q & 1), 0), k - 1);
-            const int y = min(max(vy[b] + ((q >> 1) & 1), 0), k - 1);
-            const int z = min(max(vz[b] + ((q >> 2) & 1), 0), k - 1);
-            load_record<FMT, MAXD>(c, record_offset(c, x, y, z), w[q]);
+          for (int b = 0; b < B; ++b) {
+            if (!have[b] || !alive) continue;
+            const float s = rec_sigma<FMT>(w[b], sc);
+            float r, g, bl;
+            rec_colour<FMT, MAXD>(w[b], beta, sc, r, g, bl);
+            const float sd = s * dt;
+            const float wgt = expf(-tau) * -expm1f(-sd);
+            cr = fmaf(wgt, r, cr);
+            cg = fmaf(wgt, g, cg);
+            cb = fmaf(wgt, bl, cb);
+            tau += sd;
+            if (tau > V.lim) alive = false;  // every later sample would be stopped
           }
-          if (tau > V.lim) {
-            alive = false;
-            continue;
-          }
-          float s = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+        } else {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const float wq = ((q & 1) ? wx[b] : 1.0f - wx[b]) *
-                             (((q >> 1) & 1) ? wy[b] : 1.0f - wy[b]) *
-                             (((q >> 2) & 1) ? wz[b] : 1.0f - wz[b]);
-            float rq, gq, bq;
-            rec_colour<FMT, MAXD>(w[q], beta, sc, rq, gq, bq);
-            s = fmaf(wq, rec_sigma<FMT>(w[q], sc), s);
-            r = fmaf(wq, rq, r);
-            g = fmaf(wq, gq, g);
-            bl = fmaf(wq, bq, bl);
+          for (int b = 0; b < B; ++b) {
+            if (!have[b] || !alive) continue;
+            uint32_t w[8][RW::nwords];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int x = min(max(vx[b] + (q & 1), 0), k - 1);
+              const int y = min(max(vy[b] + ((q >> 1) & 1), 0), k - 1);
+              const int z = min(max(vz[b] + ((q >> 2) & 1), 0), k - 1);
+              load_record<FMT, MAXD>(c, record_offset(c, x, y, z), w[q]);
+            }
+            float s = 0.f, r = 0.f, g = 0.f, bl = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const float wq = ((q & 1) ? wx[b] : 1.0f - wx[b]) *
+                               (((q >> 1) & 1) ? wy[b] : 1.0f - wy[b]) *
+                               (((q >> 2) & 1) ? wz[b] : 1.0f - wz[b]);
+              float rq, gq, bq;
+              rec_colour<FMT, MAXD>(w[q], beta, sc, rq, gq, bq);
+              s = fmaf(wq, rec_sigma<FMT>(w[q], sc), s);
+              r = fmaf(wq, rq, r);
+              g = fmaf(wq, gq, g);
+              bl = fmaf(wq, bq, bl);
+            }
+            const float sd = s * dt;
+            const float wgt = expf(-tau) * -expm1f(-sd);
+            cr = fmaf(wgt, r, cr);
+            cg = fmaf(wgt, g, cg);
+            cb = fmaf(wgt, bl, cb);
+            tau += sd;
+            if (tau > V.lim) alive = false;
           }
-          const float sd = s * dt;
-          const float wgt = expf(-tau) * -expm1f(-sd);
-          cr = fmaf(wgt, r, cr);
-          cg = fmaf(wgt, g, cg);
-          cb = fmaf(wgt, bl, cb);
-          tau += sd;
         }
       }
+      i += kWin;
       if (i >= N) alive = false;
     }
   }

@@ -50,6 +50,12 @@ def render_gpu(cache, view, N, eps):
     return out.cpu().numpy().reshape(-1, 4).astype(np.float64)
 
 
+def oracle_render(scene, view, N, eps, pix=None):
+    """The oracle with nearest-voxel decisions taken in the kernel's precision."""
+    return oracle.render(scene, view.K, view.c2w, view.H, view.W, view.near, view.far, N, eps,
+                         pix=pix, tol=oracle.KERNEL_TOL)
+
+
 def compare(gpu_rgba, res, tol, max_unchecked=0.01):
     """Returns (max error over checked pixels, number failing, unchecked count)."""
     err, ok = oracle.matches(gpu_rgba, res, tol)

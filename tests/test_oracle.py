@@ -368,3 +368,22 @@ def test_ambiguous_face_gives_both_candidates():
     assert first[0] == 0 and first[1] > 0   # both samples in the upper cell (reading R6)
     assert last[0] > 0 and last[1] == 0     # both in the lower cell
     np.testing.assert_array_equal(res["rgba"][0], first)
+
+
+def test_fp32_voxel_decisions_are_admissible():
+    """Taking the nearest-voxel decision in FP32 (reading R13b) yields one of
+    the results the FP64 enumeration admits, on a scene whose sample spacing is
+    commensurate with the grid (k/N = 4 voxels per sample)."""
+    spec = synth.paper_scene_spec(k=64)
+    p = synth.draw(spec)
+    slot, ss, su = synth.brick_sparse(p, 8)
+    beta = synth.beta_table(p)
+    sc = oracle.Scene(beta, k=64, sparse=(8, slot, ss, su), in_box=True)
+    v = synth.paper_orbit(4, W=64, H=64)[0]
+    a = oracle.render(sc, v.K, v.c2w, 64, 64, v.near, v.far, 16, 1e-4, tol=oracle.DEFAULT_TOL)
+    b = oracle.render(sc, v.K, v.c2w, 64, 64, v.near, v.far, 16, 1e-4, tol=oracle.KERNEL_TOL)
+    checked = (a["flags"] & oracle.UNCHECKED) == 0
+    _, ok = oracle.matches(b["rgba"], a, 1e-12)
+    assert ok[checked].all() and checked.sum() > 1000
+    assert (a["flags"] & oracle.AMBIG).sum() > 50  # the commensurate case is common
+    assert b["counts"]["unchecked_pixels"] == 0

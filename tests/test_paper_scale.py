@@ -1,0 +1,77 @@
+"""The paper-scale workload at full size (k=768, D=8, l=384, 800x800, N=192 in
+the box, 8^3 bricks), rendered exactly as bench.py times it (one
+fastnerf_render launch per view), checked on sampled pixels against the oracle
+(nearest-voxel decisions in FP32, reading R13b) computed one pixel at a time
+on a brick-sparse copy of the same scene."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+N, EPS = 192, 1e-4
+
+
+@pytest.fixture(scope="module")
+def scene():
+    import torch
+    import bench
+    spec = synth.paper_scene_spec(k=768)
+    p, beta, caches, sparse, occ = bench.build_caches(spec, ["f32", "f16", "fp8"], True, "cuda")
+    torch.cuda.synchronize()
+    assert 0.075 <= occ <= 0.085
+    yield spec, beta, caches, sparse
+    for c in caches.values():
+        c.destroy()
+
+
+def _sample(view, n, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(view.H * view.W, n, replace=False))
+
+
+def _gpu_pixels(cache, view, pix):
+    import torch
+    import paper_2103_10380_amd as fn
+    out = fn.render(cache, view.K, view.c2w, view.H, view.W, view.near, view.far, N, EPS)
+    torch.cuda.synchronize()
+    return out.reshape(-1, 4)[torch.as_tensor(pix, device="cuda")].cpu().numpy().astype(
+        np.float64)
+
+
+@pytest.mark.parametrize("vi", [0, 13, 27])
+def test_fp32_sampled_parity(scene, vi):
+    spec, beta, caches, sparse = scene
+    v = synth.paper_orbit(40)[vi]
+    pix = _sample(v, 3000, vi)
+    sc = oracle.Scene(beta, k=spec.k, sparse=sparse, in_box=True)
+    res = G.oracle_render(sc, v, N, EPS, pix=pix)
+    err, failing, unchecked = G.compare(_gpu_pixels(caches["f32"], v, pix), res, G.F32_COST_TOL)
+    assert failing == 0 and unchecked == 0, err
+    assert res["counts"]["hit"] > 1000
+
+
+@pytest.mark.parametrize("storage", ["f16", "fp8"])
+def test_reduced_precision_sampled(scene, storage):
+    """Kernel parity on the oracle's own dequantised copy, and the precision
+    cost against the FP32 inputs (FP16 max-abs 2e-3, FP8 PSNR 40 dB)."""
+    spec, beta, caches, sparse = scene
+    v = synth.paper_orbit(40)[5]
+    pix = _sample(v, 3000, 99)
+    sb, slot, ss, su = sparse
+    gpu = _gpu_pixels(caches[storage], v, pix)
+    ref32 = G.oracle_render(oracle.Scene(beta, k=spec.k, sparse=sparse, in_box=True), v, N, EPS,
+                            pix=pix)
+    if storage == "f16":  # (FP8 scales span the whole cache: kernel parity runs at k=128)
+        sq, uq, _ = oracle.dequant_cache(storage, ss, su)
+        refq = G.oracle_render(oracle.Scene(beta, k=spec.k, sparse=(sb, slot, sq, uq),
+                                            in_box=True), v, N, EPS, pix=pix)
+        err, failing, _ = G.compare(gpu, refq, G.PARITY_TOL)
+        assert failing == 0, err
+        err32, _ = oracle.matches(gpu, ref32, 1.0)
+        assert err32.max() <= G.F16_COST_TOL
+    else:
+        assert G.psnr(gpu, ref32["rgba"]) >= G.FP8_MIN_PSNR

@@ -35,7 +35,7 @@ def test_tiny_scenes_all_modes(pos_linear, dir_linear, in_box, W, H):
         gpu = G.render_gpu(cache, v, 40, 1e-3)
         sc = G.oracle_scene(sig, u, beta, pos_linear=pos_linear, dir_linear=dir_linear,
                             in_box=in_box, bg=(0.2, 0.4, 0.9))
-        res = oracle.render(sc, v.K, v.c2w, H, W, v.near, v.far, 40, 1e-3)
+        res = G.oracle_render(sc, v, 40, 1e-3)
         err, failing, _ = G.compare(gpu, res, G.PARITY_TOL)
         assert failing == 0, (brick, err)
 
@@ -46,7 +46,7 @@ def test_config1_fp32_parity():
     v = G.config1_view()
     cache = G.make_cache(sig, u, beta, brick=8)
     gpu = G.render_gpu(cache, v, 128, 1e-4)
-    res = oracle.render(G.oracle_scene(sig, u, beta), v.K, v.c2w, 200, 200, 2.0, 4.0, 128, 1e-4)
+    res = G.oracle_render(G.oracle_scene(sig, u, beta), v, 128, 1e-4)
     err, failing, unchecked = G.compare(gpu, res, G.F32_COST_TOL)
     print(f"config1 f32: max err {err:.2e}, ambiguous {res['counts']['ambiguous_pixels']}, "
           f"unchecked {unchecked}")
@@ -61,8 +61,7 @@ def test_config1_reduced_precision_kernel_parity(storage):
     v = G.config1_view()
     cache = G.make_cache(sig, u, beta, storage=storage, brick=8)
     gpu = G.render_gpu(cache, v, 128, 1e-4)
-    res = oracle.render(G.oracle_scene(sig, u, beta, storage=storage), v.K, v.c2w, 200, 200,
-                        2.0, 4.0, 128, 1e-4)
+    res = G.oracle_render(G.oracle_scene(sig, u, beta, storage=storage), v, 128, 1e-4)
     err, failing, _ = G.compare(gpu, res, G.PARITY_TOL)
     assert failing == 0, err
 
@@ -72,7 +71,7 @@ def test_config1_precision_cost():
     max-abs, FP8 at PSNR >= 40 dB; BF16 is reported."""
     sig, u, beta = G.config1_scene()
     v = G.config1_view()
-    res = oracle.render(G.oracle_scene(sig, u, beta), v.K, v.c2w, 200, 200, 2.0, 4.0, 128, 1e-4)
+    res = G.oracle_render(G.oracle_scene(sig, u, beta), v, 128, 1e-4)
     out = {}
     for storage in ("f16", "bf16", "fp8"):
         gpu = G.render_gpu(G.make_cache(sig, u, beta, storage=storage), v, 128, 1e-4)
