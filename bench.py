@@ -127,7 +127,7 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, seed
         pix = np.sort(rng.choice(v.H * v.W, pix_per_view, replace=False))
         t0 = time.perf_counter()
         r = oracle.render(sc, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, pix=pix,
-                          tol=oracle.KERNEL_TOL)
+                          tol=oracle.DEFAULT_TOL)
         t_cpu += time.perf_counter() - t0
         res.append((vi, pix, r))
         rays += len(pix)

@@ -24,13 +24,12 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 MAXCAND = 32
 HIT, AMBIG, UNCHECKED = 1, 2, 4
 
-# Default admissibility bands (reading R13): a sample within 1e-5 world units of
-# a voxel face may take either voxel; a stop point within 1e-3 of ln(1/eps) in
-# optical depth may be taken or not; nearest direction cells within 1e-5 rad.
-DEFAULT_TOL = (1e-5, 1e-5, 1e-3, 0)
-# For comparisons with the FP32 kernel: nearest-voxel decisions taken in FP32
-# (reading R13b), the other bands as above.
-KERNEL_TOL = (0.0, 1e-5, 1e-3, 1)
+# Default admissibility bands (reading R13): a sample within 1e-3 voxel of a
+# cell boundary may take either voxel (FP32 grid coordinates of the kernel are
+# good to about 3e-4 voxel at k = 768); a stop point within 1e-3 of ln(1/eps)
+# in optical depth may be taken or not; nearest direction cells within 1e-5 rad.
+DEFAULT_TOL = (1e-3, 1e-5, 1e-3)
+TIE = 1.0 / 512.0  # cell boundaries sit this many voxels below the faces (reading R6b)
 
 
 def build(verbose: bool = False) -> str:
@@ -66,7 +65,7 @@ class _View(ctypes.Structure):
 
 class _Tol(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("gamma_dir", ctypes.c_double),
-                ("tau_band", ctypes.c_double), ("fp32_voxels", ctypes.c_int32)]
+                ("tau_band", ctypes.c_double)]
 
 
 class _Counts(ctypes.Structure):
@@ -185,8 +184,7 @@ def _view(K, c2w, H, W, near, far, N, eps):
 
 def _tol(tol):
     t = _Tol()
-    t.gamma, t.gamma_dir, t.tau_band = tol[:3]
-    t.fp32_voxels = int(tol[3]) if len(tol) > 3 else 0
+    t.gamma, t.gamma_dir, t.tau_band = tol
     return t
 
 
@@ -206,7 +204,7 @@ def render(scene: Scene, K, c2w, H, W, near, far, N, eps, pix=None, tol=DEFAULT_
     ncand = np.zeros(n, dtype=np.int32) if candidates else None
     flags = np.zeros(n, dtype=np.int32)
     cnt = _Counts()
-    t = _tol(tol) if tol is not None else _tol((0.0, 0.0, 0.0, 0))
+    t = _tol(tol) if tol is not None else _tol((0.0, 0.0, 0.0))
     rc = lib().orc_render(ctypes.byref(scene.struct), ctypes.byref(v), ctypes.byref(t), n,
                           _ptr(pp), _ptr(rgba), _ptr(cand), _ptr(ncand), _ptr(flags),
                           ctypes.byref(cnt))

@@ -38,19 +38,17 @@
  *      composited with the remaining transmittance.
  *   R9/R11 RGB includes the background times the final transmittance; A = 1 - T.
  *   R10 no activation is applied to the colour of Eq. 5.
- *   R13 a sample whose position lies within gamma of a voxel face may take
- *      either neighbour, and a stop point within tau_band of ln(1/eps) may be
+ *   R13 a sample whose grid coordinate lies within gamma (voxels) of a cell
+ *      boundary may take either neighbour, and a stop point within tau_band of ln(1/eps) may be
  *      taken or not: all such variants are admissible results (the FP32 kernel
  *      cannot resolve them), and they are enumerated.
- *   R13b when the sample spacing is commensurate with the grid (k/N voxels per
- *      sample along an axis the ray crosses from face to face, e.g. k = 768,
- *      N = 192) every sample lies on a voxel face, and the nearest voxel is
- *      decided by rounding. The decision is then taken in FP32, the kernel's
- *      precision: with g0 = float((o + t0 d - bmin) h^-1), e = float(d h^-1),
- *      dt = float((t1 - t0)/N) and h^-1 = float(k/(bmax - bmin)), sample i has
- *      g = fmaf(float(i + 1/2) * dt, e, g0) per axis, is inside when
- *      0 <= g <= k and takes voxel min(floor(g), k - 1). Only this integer is
- *      taken from FP32; positions, values and compositing stay FP64.
+ *   R6b ties: when the sample spacing is commensurate with the grid (k/N
+ *      voxels per sample along an axis that the ray crosses from face to face,
+ *      e.g. k = 768, N = 192) every sample lies exactly on a voxel face. A
+ *      point on a face belongs to the upper cell (R6); so that rounding cannot
+ *      flip that choice, the cell boundaries are taken 2^-9 voxel below the
+ *      faces: the nearest voxel of grid coordinate g is min(floor(g + 2^-9),
+ *      k - 1) inside the box.
  *   R17 the transmittance sum of Eq. 1 runs over the samples before i.
  */
 #include "fastnerf_oracle.h"
@@ -156,10 +154,13 @@ static double grid_coord(const orc_scene *s, int ax, double p) {
   return (p - s->bmin[ax]) * (double)s->k / (s->bmax[ax] - s->bmin[ax]);
 }
 
+/* Cell boundaries sit this far (in voxels) below the faces (reading R6b). */
+#define ORC_TIE (1.0 / 512.0)
+
 /* Nearest voxel along one axis, -1 outside the box. */
 static int nn_coord(double g, int k) {
   if (g < 0.0 || g > (double)k) return -1;
-  int c = (int)floor(g);
+  int c = (int)floor(g + ORC_TIE);
   return c > k - 1 ? k - 1 : c;
 }
 
@@ -312,15 +313,20 @@ static void work_free(ray_work *w) {
   free(w->t);
 }
 
-/* Alternative nearest-voxel coordinate across the nearest face, if the sample
-   is within gamma (world units) of it. */
-static int nn_alternative(double g, int k, double h, double gamma, int prim, int *alt) {
-  double n = floor(g + 0.5);
-  if (n < 0.0 || n > (double)k) return 0;
-  if (fabs(g - n) * h >= gamma) return 0;
-  int below = n >= 1.0 ? (int)n - 1 : -1;
-  int above = n <= (double)(k - 1) ? (int)n : -1;
-  *alt = prim == below ? above : below;
+/* Alternative nearest-voxel coordinate across the nearest cell boundary (or
+   box face), if the grid coordinate is within gamma voxels of it. */
+static int nn_alternative(double g, int k, double gamma, int prim, int *alt) {
+  if (fabs(g) < gamma) { /* lower box face */
+    *alt = prim == -1 ? 0 : -1;
+    return 1;
+  }
+  if (fabs(g - k) < gamma) { /* upper box face */
+    *alt = prim == -1 ? k - 1 : -1;
+    return 1;
+  }
+  double gt = g + ORC_TIE, n = floor(gt + 0.5);
+  if (n < 1.0 || n > (double)(k - 1) || fabs(gt - n) >= gamma || prim < 0) return 0;
+  *alt = prim == (int)n ? (int)n - 1 : (int)n;
   return *alt != prim;
 }
 
@@ -464,24 +470,10 @@ static int place_samples(const orc_scene *s, const orc_view *v, const orc_tol *t
       g[ax] = grid_coord(s, ax, w->p[i][ax]);
       w->c[i][ax] = nn_coord(g[ax], k);
     }
-    if (!s->pos_linear && tol && tol->fp32_voxels) {
-      for (int ax = 0; ax < 3; ax++) {
-        float ih = (float)((double)k / (s->bmax[ax] - s->bmin[ax]));
-        float g0 = (float)((fma(t0, d[ax], o[ax]) - s->bmin[ax]) * (double)ih);
-        float e = (float)(d[ax] * (double)ih);
-        float dt = (float)delta;
-        float gf = fmaf(((float)i + 0.5f) * dt, e, g0);
-        w->c[i][ax] = (gf >= 0.0f && gf <= (float)k) ? (int)fminf(floorf(gf), (float)(k - 1)) : -1;
-      }
-      if (w->c[i][0] < 0 || w->c[i][1] < 0 || w->c[i][2] < 0)
-        w->c[i][0] = w->c[i][1] = w->c[i][2] = -1;
-      continue;
-    }
     if (s->pos_linear || !tol || tol->gamma <= 0.0) continue;
     int amb = 0, alts[3], has[3];
     for (int ax = 0; ax < 3; ax++) {
-      double h = (s->bmax[ax] - s->bmin[ax]) / k;
-      has[ax] = nn_alternative(g[ax], k, h, tol->gamma, w->c[i][ax], &alts[ax]);
+      has[ax] = nn_alternative(g[ax], k, tol->gamma, w->c[i][ax], &alts[ax]);
       amb += has[ax];
     }
     for (int ax = 0; ax < 3; ax++) {

@@ -64,11 +64,9 @@ typedef struct {
 } orc_view;
 
 typedef struct {
-  double gamma;         /* world units: samples this close to a voxel face may take either voxel */
+  double gamma;         /* voxels: samples this close to a cell boundary may take either voxel */
   double gamma_dir;     /* radians: same for nearest direction cells */
   double tau_band;      /* log-transmittance: stop points this close to ln(1/eps) are both admissible */
-  int32_t fp32_voxels;  /* 1: take each sample's nearest-voxel decision in FP32 (see the C source,
-                           reading R13b) instead of enumerating both sides of a face */
 } orc_tol;
 
 typedef struct {

@@ -21,6 +21,11 @@ constexpr int kMaxCh = 1 + 3 * kMaxD;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Nearest-voxel cell boundaries sit this many voxels below the faces: a point
+// on a face (or within rounding of it) takes the upper cell, also when the
+// sample spacing is commensurate with the grid and every sample lies on a face.
+constexpr float kTie = 1.0f / 512.0f;
+
 struct DevCache {
   const uint8_t *rec;
   const float *beta;

@@ -106,8 +106,9 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
           word[j] = ~0u;
           bitpos[j] = 0u;
           if (skip) {  // clamped voxel: always a valid address, even when not inside
-            const int x = min(max((int)gx, 0), k - 1), y = min(max((int)gy, 0), k - 1),
-                      z = min(max((int)gz, 0), k - 1);
+            const int x = min(max((int)(gx + kTie), 0), k - 1),
+                      y = min(max((int)(gy + kTie), 0), k - 1),
+                      z = min(max((int)(gz + kTie), 0), k - 1);
             const uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo +
                                   (uint32_t)(y >> c.oshift)) * (uint32_t)c.nbo +
                                  (uint32_t)(x >> c.oshift);
@@ -143,9 +144,9 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
               wy[b] = hy - fy0;
               wz[b] = hz - fz0;
             } else {
-              vx[b] = min((int)gx, k - 1);
-              vy[b] = min((int)gy, k - 1);
-              vz[b] = min((int)gz, k - 1);
+              vx[b] = min((int)(gx + kTie), k - 1);
+              vy[b] = min((int)(gy + kTie), k - 1);
+              vz[b] = min((int)(gz + kTie), k - 1);
             }
           }
         }
@@ -473,7 +474,7 @@ __global__ void k_lookup(DevCache c, int n, const float *__restrict__ pts,
           v[ax] = min(max((int)f + bit, 0), k - 1);
           wt *= bit ? h - f : 1.0f - (h - f);
         } else {
-          v[ax] = min((int)g[ax], k - 1);
+          v[ax] = min((int)(g[ax] + kTie), k - 1);
         }
       }
       uint32_t w[RW::nwords];

@@ -14,15 +14,22 @@ import mpmath as mp
 mp.mp.dps = 50
 
 
-def _cell_of(value, lo, hi, n):
-    """Index of the cell [lo + i h, lo + (i+1) h) containing value, by search;
-    the upper face belongs to the last cell; None outside."""
+def _cell_of(value, lo, hi, n, tie=0):
+    """Index of the cell containing value, by search over the cells
+    [lo + (i - tie) h, lo + (i + 1 - tie) h) (the first and last cells extend to
+    the box faces); None outside [lo, hi]."""
     h = (hi - lo) / n
+    if value < lo or value > hi:
+        return None
     for i in range(n):
-        a, b = lo + i * h, lo + (i + 1) * h
+        a = lo if i == 0 else lo + (i - tie) * h
+        b = hi if i == n - 1 else lo + (i + 1 - tie) * h
         if a <= value < b or (i == n - 1 and value == b):
             return i
     return None
+
+
+TIE = mp.mpf(1) / 512  # cell boundaries 2^-9 voxel below the faces (reading R6b)
 
 
 def render_pixel(sigma, u, beta, k, D, l, K, c2w, x, y, near, far, N, eps, bg,
@@ -58,7 +65,7 @@ def render_pixel(sigma, u, beta, k, D, l, K, c2w, x, y, near, far, N, eps, bg,
     for i in range(N):
         t = t0 + (i + mp.mpf(1) / 2) * delta
         p = [o[a] + t * d[a] for a in range(3)]
-        cells = [_cell_of(p[a], lo, hi, k) for a in range(3)]
+        cells = [_cell_of(p[a], lo, hi, k, TIE) for a in range(3)]
         if any(c is None for c in cells):
             sig.append(mp.mpf(0))
             col.append([mp.mpf(0)] * 3)

@@ -51,9 +51,9 @@ def render_gpu(cache, view, N, eps):
 
 
 def oracle_render(scene, view, N, eps, pix=None):
-    """The oracle with nearest-voxel decisions taken in the kernel's precision."""
+    """The oracle with the default admissibility bands (reading R13)."""
     return oracle.render(scene, view.K, view.c2w, view.H, view.W, view.near, view.far, N, eps,
-                         pix=pix, tol=oracle.KERNEL_TOL)
+                         pix=pix, tol=oracle.DEFAULT_TOL)
 
 
 def compare(gpu_rgba, res, tol, max_unchecked=0.01):
