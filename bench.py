@@ -139,6 +139,39 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, seed
     return sc, res, rays, t_cpu, totals
 
 
+def summarize_profile(paths, match=("k_render", "neg_kernel")):
+    """Compact text summary of rocprofv3 CSV output (kernel stats and counter
+    collections): per-kernel calls and durations, per-dispatch counter means."""
+    import csv
+    import glob
+    lines = []
+    for root in paths:
+        for f in sorted(glob.glob(os.path.join(root, "**", "*kernel_stats.csv"), recursive=True)):
+            lines.append(f"# kernel stats ({os.path.basename(root)})")
+            lines.append("name | calls | avg_us | min_us | max_us | total_%")
+            for r in csv.DictReader(open(f)):
+                if any(m in r["Name"] for m in match):
+                    lines.append(f"{r['Name'][:90]} | {r['Calls']} | "
+                                 f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                                 f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}")
+        for f in sorted(glob.glob(os.path.join(root, "**", "*counter_collection.csv"),
+                               recursive=True)):
+            acc = {}
+            for r in csv.DictReader(open(f)):
+                name = r.get("Kernel_Name", "")
+                if not any(m in name for m in match):
+                    continue
+                key = (name[:90], r["Counter_Name"])
+                a = acc.setdefault(key, [0.0, set()])
+                a[0] += float(r["Counter_Value"])
+                a[1].add(r.get("Dispatch_Id", r.get("Correlation_Id")))
+            lines.append(f"# counters ({os.path.basename(root)}): mean per dispatch")
+            lines.append("kernel | counter | dispatches | mean")
+            for (name, cn), (tot, ids) in sorted(acc.items()):
+                lines.append(f"{name} | {cn} | {len(ids)} | {tot / max(1, len(ids)):.6g}")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,8 +182,15 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="FP32 cache only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--cpu-pixels", type=int, default=2048, help="oracle pixels per view")
+    ap.add_argument("--cpu-pixels", type=int, default=32768, help="oracle pixels per view")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for profiler byte counters)")
+    ap.add_argument("--summarize-profile", nargs="+", metavar="DIR",
+                    help="print a summary of rocprofv3 CSV output directories and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        print(summarize_profile(args.summarize_profile))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build "
               "renders on a single MI355X; multi-GPU sharding is a design note only)",
@@ -187,6 +227,15 @@ def main():
             results[st]["outs"] = outs
         log(f"{st}: {results[st]['mrays']:.1f} Mrays/s, frame p50 "
             f"{np.percentile(frame_ms, 50):.3f} ms p99 {np.percentile(frame_ms, 99):.3f} ms")
+
+    if args.calibrate_copy:
+        # a plain streaming kernel of known size: reads 1 GiB, writes 1 GiB
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log("calibration: 3 x neg over 1 GiB (1 GiB read + 1 GiB written each)")
 
     r32 = results["f32"]
     frame_ms = r32["frame_ms"]

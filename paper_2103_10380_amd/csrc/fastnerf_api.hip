@@ -74,7 +74,7 @@ static bool finite_all(const float *v, int n) {
   return true;
 }
 
-// Per (device, stream) launch state: the self-resetting tile-queue counter and
+// Per (device, stream) launch state: the self-resetting tile-queue counters and
 // a staging area for batched view descriptors. Allocated once per stream.
 struct StreamState {
   unsigned *counter = nullptr;
@@ -98,8 +98,8 @@ fastnerf_status stream_state(hipStream_t s, StreamState **out) {
     return FASTNERF_OK;
   }
   StreamState *st = new StreamState();
-  hipError_t e = hipMalloc(&st->counter, 2 * sizeof(unsigned));
-  if (e == hipSuccess) e = hipMemset(st->counter, 0, 2 * sizeof(unsigned));
+  hipError_t e = hipMalloc(&st->counter, kQueueCounters * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(st->counter, 0, kQueueCounters * sizeof(unsigned));
   if (e == hipSuccess) e = hipEventCreateWithFlags(&st->staged, hipEventDisableTiming);
   if (e != hipSuccess) {
     delete st;
@@ -125,30 +125,41 @@ fastnerf_status stream_views(StreamState *st, int n) {
   return FASTNERF_OK;
 }
 
-int persistent_grid(const fastnerf_cache_s *c, int total_tiles) {
+// Launch shape of the render kernel for a cache: a persistent grid of as many
+// 256-thread blocks as are resident at once, capped by the work.
+struct LaunchPlan {
+  int block, grid;
+};
+
+LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles) {
   static std::mutex mu;
-  static std::map<std::pair<int, int>, int> cu_blocks;  // (device, variant) -> blocks
+  static std::map<std::pair<int, int>, int> plans;  // (device, variant) -> resident blocks
   int dev = 0;
   (void)hipGetDevice(&dev);
   const bool lin = c->desc.pos_interp == FASTNERF_LINEAR;
-  const int variant = (int)c->desc.storage * 64 + (lin ? 32 : 0) + (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
+  const int variant = (int)c->desc.storage * 64 + (lin ? 32 : 0) +
+                      (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
   int blocks;
   {
     std::lock_guard<std::mutex> g(mu);
     auto key = std::make_pair(dev, variant);
-    auto it = cu_blocks.find(key);
-    if (it == cu_blocks.end()) {
+    auto it = plans.find(key);
+    if (it == plans.end()) {
       int cus = 0;
       if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
           cus < 1)
         cus = 1;
-      it = cu_blocks.emplace(key, cus * render_occupancy((int)c->desc.storage, lin, c->desc.D))
-               .first;
+      const int per_cu = render_occupancy((int)c->desc.storage, lin, c->desc.D);
+      it = plans.emplace(key, cus * (per_cu < 1 ? 1 : per_cu)).first;
     }
     blocks = it->second;
   }
-  const int need = (total_tiles + kBlock / kWave - 1) / (kBlock / kWave);
-  return need < blocks ? (need < 1 ? 1 : need) : blocks;
+  LaunchPlan p;
+  p.block = kBlock;
+  const int wpb = p.block / kWave;
+  const int need = (total_tiles + wpb - 1) / wpb;
+  p.grid = need < blocks ? (need < 1 ? 1 : need) : blocks;
+  return p;
 }
 
 // View descriptor from K and c2w; R K^-1 is formed and kept in double.
@@ -237,12 +248,12 @@ float eps_limit(float eps) { return eps > 0.0f ? (float)log(1.0 / (double)eps) :
 fastnerf_status enqueue_render(fastnerf_cache_s *c, const RenderArgs &a0, int total_tiles,
                                StreamState *st, hipStream_t s) {
   RenderArgs a = a0;
-  const int grid = persistent_grid(c, total_tiles);
+  const LaunchPlan p = launch_plan(c, total_tiles);
   a.counter = st->counter;
-  a.nwaves = (unsigned)grid * (kBlock / kWave);
+  a.nwaves = (unsigned)p.grid * (p.block / kWave);
   a.total_tiles = total_tiles;
   hipError_t e = launch_render((int)c->desc.storage, c->desc.pos_interp == FASTNERF_LINEAR, a,
-                               grid, s);
+                               p.grid, s);
   if (e != hipSuccess) return hip_fail(e, "render launch");
   HIP_TRY(hipEventRecord(c->last_use, s));
   return FASTNERF_OK;

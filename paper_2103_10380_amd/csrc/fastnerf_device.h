@@ -63,7 +63,7 @@ struct RenderArgs {
   const DevView *views;     // batched launch: nviews views, tile_begin ascending
   int nviews;
   int total_tiles;
-  unsigned *counter;        // [0] next tile, [1] retired waves; self-resetting
+  unsigned *counter;        // tile-queue counters (kQueueCounters uints), self-resetting
   unsigned nwaves;
   const DevCache *caches;   // serving: per-scene caches (device), views[i].scene indexes it
   const int *dyn_total;     // serving: {tile count, view count} of the step (device)

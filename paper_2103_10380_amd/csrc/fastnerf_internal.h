@@ -30,7 +30,6 @@ fastnerf_status stream_state(hipStream_t s, StreamState **out);
 DevCache dev_cache(const fastnerf_cache_s *c);
 void make_view(const fastnerf_cache_s *c, const float K[9], const float c2w[12], int H, int W,
                float near_, float far_, float *out, int tile_begin, DevView *v);
-int persistent_grid(const fastnerf_cache_s *c, int total_tiles);
 fastnerf_status check_render_params(int N, float eps);
 fastnerf_status check_view(const float *K, const float *c2w, int H, int W, float near_,
                            float far_, const float *out);

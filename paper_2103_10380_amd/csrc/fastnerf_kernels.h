@@ -4,7 +4,11 @@
 
 namespace fnr {
 
+// Resident blocks per CU of the render kernel (0 if it cannot launch).
 int render_occupancy(int fmt, bool lin, int D);
+// Tile queues of a render launch and the spacing of their counters (uints):
+// the counter buffer of a stream holds kQueueCounters uints.
+constexpr int kQueueCounters = 32 * 32;
 int render_step_occupancy(bool lin, int D);
 hipError_t launch_render_step(bool lin, int D, const RenderArgs &a, int grid, hipStream_t s);
 hipError_t launch_render(int fmt, bool lin, const RenderArgs &a, int grid, hipStream_t s);

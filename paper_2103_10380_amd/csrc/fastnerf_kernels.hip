@@ -1,9 +1,10 @@
 // gfx950 kernels of the FastNeRF cached renderer.
 //
 //   k_render      the hot path: rays of 8x8 pixel tiles (one tile per wave,
-//                 tiles taken from a persistent queue), empty-space skipping on
+//                 tiles taken from persistent queues), empty-space skipping on
 //                 the brick bitgrid, record gathers, Eq. 5 colour, Eq. 1
 //                 compositing in optical depth with early termination.
+//   k_render_step the same over a serving step's views and scenes.
 //   k_absmax      per-channel |max| for FP8 scales.
 //   k_pack        FP32 slab -> padded brick-linear records in the storage format.
 //   k_occupancy   brick bitgrid from the stored densities.
@@ -18,11 +19,25 @@ namespace fnr {
 
 // Samples in flight per lane between loads and compositing: enough record
 // bytes outstanding per wave to cover HBM latency without spilling VGPRs.
-// Samples whose occupancy bits are fetched together.
-constexpr int kWin = 8;
+// Tuning (compile-time): samples whose occupancy bits are fetched together,
+// and records in flight per lane for each storage format.
+#ifndef FNR_WIN
+#define FNR_WIN 16
+#endif
+#ifndef FNR_BATCH_F32
+#define FNR_BATCH_F32 2
+#endif
+#ifndef FNR_BATCH_F16
+#define FNR_BATCH_F16 4
+#endif
+#ifndef FNR_BATCH_F8
+#define FNR_BATCH_F8 4
+#endif
+constexpr int kWin = FNR_WIN;
 
 template <int FMT, bool LIN> struct Batch {
-  static constexpr int value = LIN ? 1 : (FMT == 0 ? 2 : (FMT == 3 ? 4 : 4));
+  static constexpr int value =
+      LIN ? 1 : (FMT == 0 ? FNR_BATCH_F32 : (FMT == 3 ? FNR_BATCH_F8 : FNR_BATCH_F16));
 };
 
 // Renders the rays of one 8x8 tile (one ray per lane) of view V with cache c.
@@ -217,11 +232,48 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
   reinterpret_cast<float4 *>(V.out)[(size_t)py * W + px] = res;
 }
 
-// Takes the next tile from the persistent queue (uniform across the wave).
-__device__ __forceinline__ int next_tile(const RenderArgs &a, int lane) {
+// Independent tile queues: all waves fetching from one counter serialise on
+// that address, so tiles are dealt round-robin to kQueues counters 128 bytes
+// apart; the waves of block b take tiles q, q + R, q + 2R, ... with
+// q = b mod R.
+constexpr int kQueues = 32;
+constexpr int kQueueStride = 32;
+
+struct Queue {
+  unsigned *ctr;  // [0] tiles handed out, [1] waves retired
+  int q, R, total;
+};
+
+__device__ __forceinline__ Queue make_queue(const RenderArgs &a, int total) {
+  Queue Q;
+  Q.R = min(kQueues, (int)gridDim.x);
+  Q.q = (int)(blockIdx.x % (unsigned)Q.R);
+  Q.ctr = a.counter + Q.q * kQueueStride;
+  Q.total = total;
+  return Q;
+}
+
+// Next tile of the wave's queue (uniform), -1 when it is empty.
+__device__ __forceinline__ int queue_fetch(const Queue &Q, int lane) {
   unsigned got = 0;
-  if (lane == 0) got = atomicAdd(a.counter, 1u);
-  return (int)__builtin_amdgcn_readfirstlane(got);
+  if (lane == 0) got = atomicAdd(Q.ctr, 1u);
+  const int n = (int)__builtin_amdgcn_readfirstlane(got);
+  const long long t = (long long)Q.q + (long long)n * Q.R;
+  return t < Q.total ? (int)t : -1;
+}
+
+// The last wave of a queue to leave resets it for the next launch on this
+// stream (every wave of the queue has made its final fetch before it retires).
+__device__ __forceinline__ void queue_retire(const Queue &Q, int lane) {
+  if (lane == 0) {
+    const unsigned nb = (gridDim.x - (unsigned)Q.q + (unsigned)Q.R - 1u) / (unsigned)Q.R;
+    const unsigned nw = nb * (blockDim.x / kWave);
+    const unsigned done = atomicAdd(Q.ctr + 1, 1u);
+    if (done == nw - 1u) {
+      atomicExch(Q.ctr, 0u);
+      atomicExch(Q.ctr + 1, 0u);
+    }
+  }
 }
 
 __device__ __forceinline__ int view_of_tile(const RenderArgs &a, int tile, int nviews) {
@@ -233,25 +285,19 @@ __device__ __forceinline__ int view_of_tile(const RenderArgs &a, int tile, int n
   return lo;
 }
 
-// The last wave to leave resets the queue for the next launch on this stream
-// (every wave has made its final fetch before it retires).
-__device__ __forceinline__ void retire(const RenderArgs &a, int lane) {
-  if (lane == 0) {
-    const unsigned done = atomicAdd(a.counter + 1, 1u);
-    if (done == a.nwaves - 1) {
-      atomicExch(a.counter, 0u);
-      atomicExch(a.counter + 1, 0u);
-    }
-  }
-}
-
-// One cache, one storage format: single views (inline descriptor) or batches.
+// One cache, one storage format: single views (inline descriptor) or a batch
+// of views in one launch. Each wave renders one 8x8 tile at a time, one ray
+// per lane, taking tiles from its queue until the queue is empty.
+#ifndef FNR_MIN_WAVES
+#define FNR_MIN_WAVES 1
+#endif
 template <int FMT, int MAXD, bool LIN>
-__global__ void __launch_bounds__(kBlock) k_render(RenderArgs a) {
+__global__ void __launch_bounds__(kBlock, FNR_MIN_WAVES) k_render(RenderArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
+  const Queue Q = make_queue(a, a.total_tiles);
   for (;;) {
-    const int tile = next_tile(a, lane);
-    if (tile >= a.total_tiles) break;
+    const int tile = queue_fetch(Q, lane);
+    if (tile < 0) break;
     if (a.views) {
       const DevView V = a.views[view_of_tile(a, tile, a.nviews)];
       render_tile<FMT, MAXD, LIN>(a, a.c, V, tile - V.tile_begin + V.tile_offset, lane);
@@ -259,7 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_render(RenderArgs a) {
       render_tile<FMT, MAXD, LIN>(a, a.c, a.v0, tile, lane);
     }
   }
-  retire(a, lane);
+  queue_retire(Q, lane);
 }
 
 // Serving step: tile ranges of many views over several resident caches of any
@@ -270,9 +316,10 @@ __global__ void __launch_bounds__(kBlock) k_render_step(RenderArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int total = __builtin_amdgcn_readfirstlane(a.dyn_total[0]);
   const int nviews = __builtin_amdgcn_readfirstlane(a.dyn_total[1]);
+  const Queue Q = make_queue(a, total);
   for (;;) {
-    const int tile = next_tile(a, lane);
-    if (tile >= total) break;
+    const int tile = queue_fetch(Q, lane);
+    if (tile < 0) break;
     const DevView V = a.views[view_of_tile(a, tile, nviews)];
     const DevCache c = a.caches[V.scene];
     const int lt = tile - V.tile_begin + V.tile_offset;
@@ -283,7 +330,7 @@ __global__ void __launch_bounds__(kBlock) k_render_step(RenderArgs a) {
       default: render_tile<3, MAXD, LIN>(a, c, V, lt, lane); break;
     }
   }
-  retire(a, lane);
+  queue_retire(Q, lane);
 }
 
 // ------------------------------------------------------------------ cache build
@@ -582,7 +629,7 @@ int render_step_occupancy(bool lin, int D) {
 }
 
 int render_occupancy(int fmt, bool lin, int D) {
-  int occ = 1;
+  int occ = 0;
   (void)dispatch(fmt, lin, D, nullptr, 0, nullptr, &occ);
   return occ;
 }

@@ -116,8 +116,8 @@ class GpuExecutor : public fs::Executor {
     HIP_CHECK(hipHostMalloc(&g->h_table, table_bytes_, hipHostMallocDefault));
     memset(g->h_table, 0, table_bytes_);
     HIP_CHECK(hipMalloc(&g->d_table, table_bytes_));
-    HIP_CHECK(hipMalloc(&g->counter, 2 * sizeof(unsigned)));
-    HIP_CHECK(hipMemset(g->counter, 0, 2 * sizeof(unsigned)));
+    HIP_CHECK(hipMalloc(&g->counter, kQueueCounters * sizeof(unsigned)));
+    HIP_CHECK(hipMemset(g->counter, 0, kQueueCounters * sizeof(unsigned)));
     const bool lin = key & 2;
     const int D = (key & 1) ? 16 : 8;
     const int grid = cus_ * render_step_occupancy(lin, D);
