@@ -114,29 +114,49 @@ def time_orbit(fn, cache, views, N, eps, steps, warmup):
     return wall, frame_ms, outs
 
 
-def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, seed=11):
-    """The FP64 oracle, single-threaded, on random pixels of every view; stops
-    at the time budget after completing a whole view."""
+def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs, seed=11):
+    """The FP64 oracle, single-threaded, on random pixels of every view (stops
+    at the time budget after completing a whole view). Each view's oracle
+    result is compared at once with the GPU renders in ``outs`` (storage ->
+    list of [H,W,4] device tensors) and only the summary is kept."""
     import oracle
+    import torch
     sb, slot, ss, su = sparse
     sc = oracle.Scene(beta, k=spec.k, sparse=(sb, slot, ss, su), in_box=True, occ_brick=8)
     rng = np.random.default_rng(seed)
-    res, done_views, rays, t_cpu = [], 0, 0, 0.0
-    totals = dict(hit=0, occ_samples=0, rays=0)
+    rays, t_cpu, nviews = 0, 0.0, 0
+    totals = dict(hit=0, occ_samples=0, rays=0, pixels=0)
+    f32 = dict(worst=0.0, fails=0, checked=0)
+    other = {st: dict(worst=0.0, se=0.0, n=0) for st in outs if st != "f32"}
     for vi, v in enumerate(views):
         pix = np.sort(rng.choice(v.H * v.W, pix_per_view, replace=False))
         t0 = time.perf_counter()
         r = oracle.render(sc, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, pix=pix,
                           tol=oracle.DEFAULT_TOL)
         t_cpu += time.perf_counter() - t0
-        res.append((vi, pix, r))
         rays += len(pix)
-        for key in totals:
+        nviews += 1
+        for key in ("hit", "occ_samples", "rays"):
             totals[key] += r["counts"][key]
-        done_views += 1
+        totals["pixels"] += v.H * v.W
+        idx = torch.as_tensor(pix, device=outs["f32"][vi].device)
+        g = outs["f32"][vi].reshape(-1, 4)[idx].cpu().numpy().astype(np.float64)
+        err, ok = oracle.matches(g, r, 1e-4)
+        unchecked = (r["flags"] & oracle.UNCHECKED) != 0
+        f32["fails"] += int((~ok & ~unchecked).sum())
+        f32["checked"] += int((~unchecked).sum())
+        if (~unchecked).any():
+            f32["worst"] = max(f32["worst"], float(err[~unchecked].max()))
+        for st, acc in other.items():
+            g = outs[st][vi].reshape(-1, 4)[idx].cpu().numpy().astype(np.float64)
+            err, _ = oracle.matches(g, r, 1.0)
+            acc["worst"] = max(acc["worst"], float(err.max()))
+            acc["se"] += float(np.sum((g[:, :3] - r["rgba"][:, :3]) ** 2))
+            acc["n"] += g.shape[0] * 3
+        del r
         if t_cpu >= seconds:
             break
-    return sc, res, rays, t_cpu, totals
+    return rays, t_cpu, nviews, totals, f32, other
 
 
 def summarize_profile(paths, match=("k_render", "neg_kernel")):
@@ -172,6 +192,41 @@ def summarize_profile(paths, match=("k_render", "neg_kernel")):
     return "\n".join(lines)
 
 
+def counter_means(root, counter):
+    """Mean per dispatch of one rocprofv3 counter, per kernel name."""
+    import csv
+    import glob
+    acc = {}
+    for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            a = acc.setdefault(r.get("Kernel_Name", ""), [0.0, set()])
+            a[0] += float(r["Counter_Value"])
+            a[1].add(r.get("Dispatch_Id", r.get("Correlation_Id")))
+    return {name: tot / max(1, len(ids)) for name, (tot, ids) in acc.items()}
+
+
+def pmc_traffic(fetch_dir, write_dir, kernel="k_render<0, 8, false>", calib="neg_kernel"):
+    """HBM bytes per launch of the render kernel from FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    calibration kernel (torch.neg over 2^28 floats: 1 GiB read, 1 GiB written)."""
+    out = {}
+    for key, root, cn in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        m = counter_means(root, cn)
+        kr = [v for n, v in m.items() if kernel in n]
+        kc = [v for n, v in m.items() if calib in n]
+        if len(kr) != 1 or len(kc) != 1:
+            raise SystemExit(f"{cn}: expected one render and one calibration kernel, got "
+                             f"{len(kr)} and {len(kc)}")
+        factor = (1 << 30) / (kc[0] * 1024.0)
+        out[key] = dict(kib_per_dispatch=kr[0], calib_kib_per_dispatch=kc[0],
+                        calib_factor=factor, bytes=kr[0] * 1024.0 * factor)
+    return {"kernel": kernel, "kernel_digest": kernel_digest(),
+            "hbm_bytes_per_launch": round(out["fetch"]["bytes"] + out["write"]["bytes"]),
+            "fetch": out["fetch"], "write": out["write"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,15 +236,21 @@ def main():
     ap.add_argument("--k", type=int, default=768)
     ap.add_argument("--no-variants", action="store_true", help="FP32 cache only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--cpu-pixels", type=int, default=32768, help="oracle pixels per view")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle pixels per view")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for profiler byte counters)")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DIR",
                     help="print a summary of rocprofv3 CSV output directories and exit")
+    ap.add_argument("--pmc-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the render kernel's calibrated HBM bytes per launch (JSON) "
+                         "from FETCH_SIZE and WRITE_SIZE runs made with --calibrate-copy")
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile))
+        return
+    if args.pmc_traffic:
+        print(json.dumps(pmc_traffic(*args.pmc_traffic), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build "
@@ -268,52 +329,32 @@ def main():
 
     # ---------------------------------------------------------------- oracle leg
     units = None
+    psnr_in = {}
     if not args.no_cpu:
-        sc, res, rays, t_cpu, totals = oracle_sample(beta, sparse, spec, views, N, eps,
-                                                     args.cpu_pixels, args.cpu_seconds)
+        outs_all = {"f32": outs_f32}
+        outs_all.update({st: results[st]["outs"] for st in storages if st != "f32"})
+        rays, t_cpu, nv, totals, f32, other = oracle_sample(
+            beta, sparse, spec, views, N, eps, args.cpu_pixels, args.cpu_seconds, outs_all)
         line["cpu_baseline"] = {
             "value": round(rays / t_cpu / 1e6, 5), "unit": "Mrays/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"{rays} random pixels ({args.cpu_pixels} per view over "
-                       f"{len(res)} views) of the same workload, FP64 single-threaded, "
+            "sample": (f"{rays} random pixels ({args.cpu_pixels} per view over the first "
+                       f"{nv} views) of the same workload, FP64 single-threaded, "
                        f"{t_cpu:.1f} s"),
         }
         # algorithmic bytes per launch: records of samples in occupied bricks,
-        # the four direction cells per hit ray, the RGBA write
-        stride, payload = caches["f32"].record_bytes
-        frac = totals["rays"] / rays
-        pix_total = sum(views[vi].H * views[vi].W for vi, _, _ in res)
-        scale = pix_total / totals["rays"] / len(res)
-        occ_per_view = totals["occ_samples"] * scale
-        hit_per_view = totals["hit"] * scale
-        units = dict(occ_samples=occ_per_view, hit_rays=hit_per_view,
-                     rays=pix_total / len(res))
-        # sampled parity of the timed renders
-        import oracle
-        worst, fails, checked, psnr_in = 0.0, 0, 0, {}
-        for vi, pix, r in res:
-            g = outs_f32[vi].reshape(-1, 4)[torch.as_tensor(pix, device="cuda")].cpu().numpy()
-            err, ok = oracle.matches(g.astype(np.float64), r, 1e-4)
-            unchecked = (r["flags"] & oracle.UNCHECKED) != 0
-            fails += int((~ok & ~unchecked).sum())
-            checked += int((~unchecked).sum())
-            worst = max(worst, float(err[~unchecked].max()))
-        line["parity"] = {"pixels": checked, "max_abs_err": worst, "failing": fails,
-                          "tol": 1e-4, "reference": "FP64 oracle, FP32 cache"}
-        for st in storages:
-            if st == "f32":
-                continue
-            errs, mse = [], []
-            for vi, pix, r in res:
-                g = results[st]["outs"][vi].reshape(-1, 4)[
-                    torch.as_tensor(pix, device="cuda")].cpu().numpy().astype(np.float64)
-                err, _ = oracle.matches(g, r, 1.0)
-                errs.append(err.max())
-                mse.append(np.mean((g[:, :3] - r["rgba"][:, :3]) ** 2))
-            m = float(np.mean(mse))
-            psnr_in[st] = dict(max_abs_err=float(max(errs)),
+        # the four direction cells per hit ray, the RGBA write (sampled counts
+        # scaled to whole views)
+        scale = totals["pixels"] / totals["rays"] / nv
+        units = dict(occ_samples=totals["occ_samples"] * scale, hit_rays=totals["hit"] * scale,
+                     rays=totals["pixels"] / nv)
+        line["parity"] = {"pixels": f32["checked"], "max_abs_err": f32["worst"],
+                          "failing": f32["fails"], "tol": 1e-4,
+                          "reference": "FP64 oracle, FP32 cache"}
+        for st, acc in other.items():
+            m = acc["se"] / max(1, acc["n"])
+            psnr_in[st] = dict(max_abs_err=acc["worst"],
                                psnr_db=(float("inf") if m == 0 else 10 * np.log10(1 / m)))
-        _ = frac
     # ---------------------------------------------------------------- roofline
     if units is not None:
         stride, payload = caches["f32"].record_bytes
