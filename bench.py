@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--views", type=int, default=40)
     ap.add_argument("--k", type=int, default=768)
     ap.add_argument("--no-variants", action="store_true", help="FP32 cache only")
+    ap.add_argument("--storages", default="f32,f16,fp8",
+                    help="comma-separated cache formats to time (f32 is always included)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle pixels per view")
@@ -267,7 +269,9 @@ def main():
     N, eps = 192, 1e-4
     spec = synth.paper_scene_spec(k=args.k)
     views = synth.paper_orbit(args.views)
-    storages = ["f32"] if args.no_variants else ["f32", "f16", "fp8"]
+    storages = ["f32"] + [st for st in args.storages.split(",") if st and st != "f32"]
+    if args.no_variants:
+        storages = ["f32"]
     t0 = time.perf_counter()
     p, beta, caches, sparse, occ = build_caches(spec, storages, not args.no_cpu, "cuda")
     torch.cuda.synchronize()

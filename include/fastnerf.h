@@ -78,8 +78,8 @@ typedef struct {
   float bbox_min[3], bbox_max[3];
   fastnerf_dtype storage;    /* position-cache storage; beta is FP32 */
   fastnerf_interp pos_interp, dir_interp;
-  int32_t brick;             /* occupancy brick edge in voxels (power of two, k % brick == 0);
-                                0 = no empty-space skipping */
+  int32_t brick;             /* occupancy brick edge in voxels (power of two, k % brick == 0,
+                                k / brick <= 1024); 0 = no empty-space skipping */
   fastnerf_sample_mode sample_mode;
   float background[3];
 } fastnerf_cache_desc;
@@ -109,7 +109,8 @@ fastnerf_status fastnerf_cache_upload_slab(fastnerf_cache cache, int32_t z0, int
                                            const float *sigma, const float *u, hipStream_t stream);
 fastnerf_status fastnerf_cache_finalize(fastnerf_cache cache, hipStream_t stream);
 
-/* Device bytes held by the cache (records, direction cache, bitgrid, scales). */
+/* Device bytes held by the cache (records, direction cache, bitgrid, distance
+ * field, scales). */
 fastnerf_status fastnerf_cache_bytes(fastnerf_cache cache, uint64_t *resident);
 /* Bytes per stored voxel record (padded) and of its payload, (1+3D)*size(storage). */
 fastnerf_status fastnerf_cache_record_bytes(fastnerf_cache cache, int32_t *stride,
@@ -122,6 +123,13 @@ fastnerf_status fastnerf_cache_readback(fastnerf_cache cache, float *sigma, floa
 /* Occupancy bitgrid (host copy): nbricks^3 bits, brick index (bz*n + by)*n + bx,
  * bit b in word b/32. words must hold ceil(n^3/32) entries. */
 fastnerf_status fastnerf_cache_occupancy(fastnerf_cache cache, uint32_t *words, int32_t *n);
+/* Empty-space distance field (host copy, after finalize): one byte per brick,
+ * same brick order as the bitgrid, holding the max-norm (Chebyshev) distance in
+ * bricks to the nearest occupied brick: 0 for an occupied brick, capped at 63.
+ * The renderer skips samples with it; output is unchanged by the skipping
+ * (Sec. 4: the caches are sparse, empty space is never sampled). dist must hold
+ * n^3 bytes; n receives the bricks per axis (0 without a bitgrid). Test hook. */
+fastnerf_status fastnerf_cache_skip_distance(fastnerf_cache cache, uint8_t *dist, int32_t *n);
 /* Waits for renders that use the cache, then frees it. */
 fastnerf_status fastnerf_cache_destroy(fastnerf_cache cache);
 

@@ -53,6 +53,7 @@ SYMBOLS = {
     "fastnerf_cache_record_bytes": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "fastnerf_cache_readback": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "fastnerf_cache_occupancy": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
+    "fastnerf_cache_skip_distance": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
     "fastnerf_cache_destroy": (_i32, [_vp]),
     "fastnerf_render": (_i32, [_vp, _pf, _pf, _i32, _i32, _f32, _f32, _i32, _f32, _vp, _vp]),
     "fastnerf_render_batch": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _vp,
@@ -85,8 +86,6 @@ def lib():
             _b.build()
         L = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
         for name, (res, args) in SYMBOLS.items():
-            if not hasattr(L, name) and name.startswith(("fastnerf_serve", "fastnerf_server")):
-                continue  # serving entry points are optional in a partial build
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
@@ -201,6 +200,16 @@ class Cache:
         check(lib().fastnerf_cache_occupancy(self.handle, _ptr(words), ctypes.byref(n)))
         bits = np.unpackbits(words.view(np.uint8), bitorder="little")[:nb ** 3]
         return bits.reshape(nb, nb, nb).astype(bool)
+
+    def skip_distance(self):
+        """Per-brick max-norm distance (in bricks) to the nearest occupied
+        brick, capped at 63: uint8 [nb, nb, nb] indexed [z, y, x]."""
+        n = ctypes.c_int32()
+        check(lib().fastnerf_cache_skip_distance(self.handle, None, ctypes.byref(n)))
+        nb = n.value
+        d = np.zeros(max(1, nb ** 3), np.uint8)
+        check(lib().fastnerf_cache_skip_distance(self.handle, _ptr(d), ctypes.byref(n)))
+        return d[:nb ** 3].reshape(nb, nb, nb)
 
     def destroy(self):
         if self.handle:

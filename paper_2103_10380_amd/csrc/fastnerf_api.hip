@@ -212,14 +212,16 @@ DevCache dev_cache(const fastnerf_cache_s *c) {
   const fastnerf_cache_desc &ds = c->desc;
   d.rec = c->rec;
   d.beta = c->beta;
-  d.occ = c->desc.brick > 0 ? c->occ : nullptr;
+  d.occ = c->occ;
+  d.dist = c->dist;
   d.scales = c->scales;
   d.k = ds.k;
   d.D = ds.D;
   d.l = ds.l;
+  d.bq = (ds.D + 3) / 4;
   d.nbl = c->nbl;
-  d.nbo = c->nbo;
-  d.oshift = c->oshift;
+  d.nbo = c->desc.brick > 0 ? c->nbo : 1;
+  d.oshift = c->desc.brick > 0 ? c->oshift : 30;
   d.rec_shift = c->rec_shift;
   d.nchunk = c->nchunk;
   d.kf = (float)ds.k;
@@ -275,6 +277,9 @@ static fastnerf_status validate_desc(const fastnerf_cache_desc *d) {
   if (d->brick < 0 || (d->brick > 0 && ((d->brick & (d->brick - 1)) || d->k % d->brick)))
     return fail(FASTNERF_EINVAL, "brick %d must be 0 or a power of two dividing k = %d",
                 d->brick, d->k);
+  if (d->brick > 0 && d->k / d->brick > 1024)
+    return fail(FASTNERF_EINVAL, "k / brick = %d exceeds 1024 bricks per axis",
+                d->k / d->brick);
   for (int a = 0; a < 3; ++a)
     if (!isfinite(d->bbox_min[a]) || !isfinite(d->bbox_max[a]) ||
         !(d->bbox_min[a] < d->bbox_max[a]) || !isfinite(d->background[a]))
@@ -294,11 +299,13 @@ extern "C" fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc
   c->desc = *desc;
   const int sz = desc->storage == FASTNERF_F32 ? 4 : desc->storage == FASTNERF_FP8_E4M3 ? 1 : 2;
   c->payload = (1 + 3 * desc->D) * sz;
+  // records hold the chunks that the kernels for this component count load
+  // (zero past the payload); the stride is the next power of two
+  c->nchunk = ((1 + 3 * maxd_class(desc->D)) * sz + 15) / 16;
   int stride = 16;
-  while (stride < c->payload) stride <<= 1;
+  while (stride < c->nchunk * 16) stride <<= 1;
   c->stride = stride;
   c->rec_shift = ilog2((uint64_t)stride);
-  c->nchunk = (c->payload + 15) / 16;
   c->nbl = (desc->k + 7) / 8;
   if (desc->brick > 0) {
     c->oshift = ilog2((uint64_t)desc->brick);
@@ -309,34 +316,42 @@ extern "C" fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc
   }
   const uint64_t nrec = (uint64_t)c->nbl * c->nbl * c->nbl * 512ull;
   const uint64_t rec_bytes = nrec * (uint64_t)stride;
-  const uint64_t beta_bytes = (uint64_t)desc->l * desc->l * desc->D * sizeof(float);
+  const int dp = (desc->D + 3) / 4 * 4;  // direction-cache row, padded to 16 bytes
+  const uint64_t beta_bytes = (uint64_t)desc->l * desc->l * dp * sizeof(float);
   const uint64_t nbits = (uint64_t)c->nbo * c->nbo * c->nbo;
   const uint64_t occ_bytes = ((nbits + 31) / 32 + 1) * 4;
+  const uint64_t dist_bytes = nbits > 0 ? nbits : 1;
   const int nch = 1 + 3 * desc->D;
   hipError_t e = hipMalloc(&c->rec, rec_bytes);
   if (e == hipSuccess) e = hipMalloc(&c->beta, beta_bytes);
   if (e == hipSuccess) e = hipMalloc(&c->occ, occ_bytes);
-  if (e == hipSuccess) e = hipMalloc(&c->scales, sizeof(float) * nch);
+  if (e == hipSuccess) e = hipMalloc(&c->dist, dist_bytes);
+  if (e == hipSuccess) e = hipMalloc(&c->scales, sizeof(float) * kMaxCh);
   if (e == hipSuccess) e = hipMalloc(&c->amax, sizeof(unsigned) * nch);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->last_use, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMemsetAsync(c->rec, 0, rec_bytes, stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->occ, 0, occ_bytes, stream);
+  // without a bitgrid the kernels read one all-ones word and one zero distance
+  if (e == hipSuccess) e = hipMemsetAsync(c->occ, desc->brick > 0 ? 0 : 0xFF, occ_bytes, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->dist, 0, dist_bytes, stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->amax, 0, sizeof(unsigned) * nch, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->beta, beta, beta_bytes, hipMemcpyDefault, stream);
-  if (e == hipSuccess && desc->storage != FASTNERF_FP8_E4M3) {
-    std::vector<float> ones(nch, 1.0f);
-    e = hipMemcpyAsync(c->scales, ones.data(), sizeof(float) * nch, hipMemcpyHostToDevice,
+  if (e == hipSuccess) e = hipMemsetAsync(c->beta, 0, beta_bytes, stream);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(c->beta, dp * sizeof(float), beta, desc->D * sizeof(float),
+                         desc->D * sizeof(float), (size_t)desc->l * desc->l, hipMemcpyDefault,
+                         stream);
+  std::vector<float> ones(kMaxCh, 1.0f);  // FP8 overwrites the first 1 + 3D
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->scales, ones.data(), sizeof(float) * kMaxCh, hipMemcpyHostToDevice,
                        stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    c->scales_ready = true;
-  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (desc->storage != FASTNERF_FP8_E4M3) c->scales_ready = true;
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     fastnerf_status r = hip_fail(e, "cache allocation");
     fastnerf_cache_destroy(c);
     return r;
   }
-  c->resident = rec_bytes + beta_bytes + occ_bytes + sizeof(float) * nch;
+  c->resident = rec_bytes + beta_bytes + occ_bytes + dist_bytes + sizeof(float) * kMaxCh;
   c->occ_bytes = occ_bytes;
   (void)hipGetDevice(&c->device);
   *out = c;
@@ -427,6 +442,14 @@ extern "C" fastnerf_status fastnerf_cache_finalize(fastnerf_cache c, hipStream_t
     hipError_t e = launch_occupancy((int)c->desc.storage, dc,
                                     c->desc.pos_interp == FASTNERF_LINEAR ? 1 : 0, c->occ, s);
     if (e != hipSuccess) return hip_fail(e, "occupancy");
+    const uint64_t nbr = (uint64_t)c->nbo * c->nbo * c->nbo;
+    uint8_t *tmp = nullptr;
+    e = hipMalloc(&tmp, nbr);
+    if (e != hipSuccess) return hip_fail(e, "distance scratch");
+    e = launch_distance(dc, c->occ, c->dist, tmp, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "distance field");
   }
   HIP_TRY(hipStreamSynchronize(s));
   c->finalized = true;
@@ -494,6 +517,17 @@ extern "C" fastnerf_status fastnerf_cache_occupancy(fastnerf_cache c, uint32_t *
   return FASTNERF_OK;
 }
 
+extern "C" fastnerf_status fastnerf_cache_skip_distance(fastnerf_cache c, uint8_t *dist,
+                                                        int32_t *n) {
+  if (!c || !n) return fail(FASTNERF_EINVAL, "null argument");
+  if (!c->finalized) return fail(FASTNERF_EINVAL, "cache not finalized");
+  *n = c->desc.brick > 0 ? c->nbo : 0;
+  if (c->desc.brick == 0 || !dist) return FASTNERF_OK;
+  const uint64_t nbr = (uint64_t)c->nbo * c->nbo * c->nbo;
+  HIP_TRY(hipMemcpy(dist, c->dist, nbr, hipMemcpyDeviceToHost));
+  return FASTNERF_OK;
+}
+
 extern "C" fastnerf_status fastnerf_cache_destroy(fastnerf_cache c) {
   if (!c) return fail(FASTNERF_EINVAL, "null cache");
   if (c->last_use) {
@@ -503,6 +537,7 @@ extern "C" fastnerf_status fastnerf_cache_destroy(fastnerf_cache c) {
   if (c->rec) (void)hipFree(c->rec);
   if (c->beta) (void)hipFree(c->beta);
   if (c->occ) (void)hipFree(c->occ);
+  if (c->dist) (void)hipFree(c->dist);
   if (c->scales) (void)hipFree(c->scales);
   if (c->amax) (void)hipFree(c->amax);
   delete c;

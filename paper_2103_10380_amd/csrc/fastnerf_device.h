@@ -5,9 +5,13 @@
 // in 64 B, FP8 25 B in 32 B) so that a record never straddles a 128-byte line.
 // Records are stored brick-linear in 8^3 bricks (512 consecutive records per
 // brick, x fastest inside), so the rays of an 8x8 pixel tile, which sample
-// nearby voxels, touch few DRAM pages. Direction cache: FP32 [l][l][D].
+// nearby voxels, touch few DRAM pages. Direction cache: FP32 [l][l][Dp] with
+// rows padded with zeros to Dp = 4 ceil(D/4) floats, so a cell is whole 16-byte
+// loads.
 // Occupancy: one bit per brick of 2^oshift voxels, set when any voxel of the
 // brick (widened by one voxel for trilinear lookups) has a stored sigma > 0.
+// Distance field: one byte per brick, the Chebyshev distance in bricks to the
+// nearest occupied brick (0 = occupied, capped at kDistCap).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,17 +30,26 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // sample spacing is commensurate with the grid and every sample lies on a face.
 constexpr float kTie = 1.0f / 512.0f;
 
+// Largest stored brick distance (one byte per brick).
+constexpr int kDistCap = 63;
+
+// Template component count of the kernels that render a cache with D
+// components; records are laid out for it.
+__host__ __device__ constexpr int maxd_class(int D) { return D <= 4 ? 4 : (D <= 8 ? 8 : 16); }
+
 struct DevCache {
   const uint8_t *rec;
   const float *beta;
-  const uint32_t *occ;   // nullptr: no empty-space skipping
-  const float *scales;   // 1 + 3D per-channel scales (FP8), ones otherwise
+  const uint32_t *occ;   // occupancy bits (one all-ones word without a bitgrid)
+  const uint8_t *dist;   // per-brick distance to the nearest occupied brick (one 0 without)
+  const float *scales;   // kMaxCh per-channel scales (FP8; ones past 1 + 3D and otherwise)
   int k, D, l;
+  int bq;                // 16-byte chunks per direction cell (rows of 4 ceil(D/4) floats)
   int nbl;               // layout bricks per axis
-  int nbo;               // occupancy bricks per axis
-  int oshift;            // log2 occupancy brick edge
+  int nbo;               // occupancy bricks per axis (1 without a bitgrid)
+  int oshift;            // log2 occupancy brick edge (30 without a bitgrid)
   int rec_shift;         // log2 record stride in bytes
-  int nchunk;            // 16-byte chunks holding the payload
+  int nchunk;            // 16-byte chunks per record: RecWords<fmt, maxd_class(D)>::nchunk
   float kf;              // k as float
   float bmin[3], bmax[3], inv_h[3];
   float th_scale, ph_scale;  // l/pi, l/(2 pi)
@@ -122,22 +135,18 @@ __device__ inline uint64_t record_offset(const DevCache &c, int x, int y, int z)
   return (((uint64_t)lb << 9) | li) << c.rec_shift;
 }
 
-__device__ inline bool occupied(const DevCache &c, int x, int y, int z) {
-  if (!c.occ) return true;
-  uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo + (uint32_t)(y >> c.oshift)) *
-                     (uint32_t)c.nbo +
-                 (uint32_t)(x >> c.oshift);
-  return (__ldg(c.occ + (bit >> 5)) >> (bit & 31)) & 1u;
-}
-
+// Records of a cache rendered with MAXD hold RecWords<FMT, MAXD>::nchunk
+// chunks (zero past the payload), so the loads are unconditional. They are
+// ordinary (L1-allocating) loads: the chunks of one record share a cache line,
+// and with non-temporal loads every 16-byte chunk went to L2 on its own, which
+// halved the speed of the render.
 template <int FMT, int MAXD>
 __device__ inline void load_record(const DevCache &c, uint64_t off, uint32_t *w) {
   using RW = RecWords<FMT, MAXD>;
   const u32x4 *p = reinterpret_cast<const u32x4 *>(c.rec + off);
 #pragma unroll
   for (int q = 0; q < RW::nchunk; ++q) {
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (q < c.nchunk) v = __builtin_nontemporal_load(p + q);
+    const u32x4 v = p[q];
     w[4 * q + 0] = v.x;
     w[4 * q + 1] = v.y;
     w[4 * q + 2] = v.z;
@@ -145,32 +154,42 @@ __device__ inline void load_record(const DevCache &c, uint64_t off, uint32_t *w)
   }
 }
 
-// sigma of a loaded record (scaled)
+// Per-ray colour weights: beta[d] for FP32/FP16/BF16 records; for E4M3
+// records the channel scales are folded in once per ray,
+// w[3d + ch] = beta[d] * scale[1 + 3d + ch], so a sample costs no scale
+// multiplies.
+template <int FMT, int MAXD> struct ColourWeights {
+  static constexpr int n = FMT == 3 ? 3 * MAXD : MAXD;
+};
+
+// sigma of a loaded record; s0 is the sigma channel's scale (E4M3 only)
 template <int FMT>
-__device__ inline float rec_sigma(const uint32_t *w, const float *sc) {
+__device__ inline float rec_sigma(const uint32_t *w, float s0) {
   float s = Fmt<FMT>::get(w, 0);
-  if (FMT == 3) s *= sc[0];
+  if (FMT == 3) s *= s0;
   return s;
 }
 
-// colour beta . (u, v, w) of a loaded record (Eq. 5); beta[d] = 0 for d >= D
+// colour beta . (u, v, w) of a loaded record (Eq. 5) with the per-ray weights
+// above; weights are 0 for d >= D
 template <int FMT, int MAXD>
-__device__ inline void rec_colour(const uint32_t *w, const float *beta, const float *sc,
-                                  float &r, float &g, float &b) {
+__device__ inline void rec_colour(const uint32_t *w, const float *cw, float &r, float &g,
+                                  float &b) {
   float cr = 0.f, cg = 0.f, cb = 0.f;
 #pragma unroll
   for (int d = 0; d < MAXD; ++d) {
-    float ur = Fmt<FMT>::get(w, 1 + 3 * d + 0);
-    float ug = Fmt<FMT>::get(w, 1 + 3 * d + 1);
-    float ub = Fmt<FMT>::get(w, 1 + 3 * d + 2);
+    const float ur = Fmt<FMT>::get(w, 1 + 3 * d + 0);
+    const float ug = Fmt<FMT>::get(w, 1 + 3 * d + 1);
+    const float ub = Fmt<FMT>::get(w, 1 + 3 * d + 2);
     if (FMT == 3) {
-      ur *= sc[1 + 3 * d + 0];
-      ug *= sc[1 + 3 * d + 1];
-      ub *= sc[1 + 3 * d + 2];
+      cr = fmaf(cw[3 * d + 0], ur, cr);
+      cg = fmaf(cw[3 * d + 1], ug, cg);
+      cb = fmaf(cw[3 * d + 2], ub, cb);
+    } else {
+      cr = fmaf(cw[d], ur, cr);
+      cg = fmaf(cw[d], ug, cg);
+      cb = fmaf(cw[d], ub, cb);
     }
-    cr = fmaf(beta[d], ur, cr);
-    cg = fmaf(beta[d], ug, cg);
-    cb = fmaf(beta[d], ub, cb);
   }
   r = cr;
   g = cg;
@@ -215,18 +234,32 @@ __device__ inline void dir_cell_weights(const DevCache &c, float dx, float dy, f
 template <int MAXD>
 __device__ inline void dir_lookup(const DevCache &c, float dx, float dy, float dz,
                                   float *beta) {
+  constexpr int NQ = MAXD / 4;
   int cell[4];
   float wt[4];
   dir_cell_weights(c, dx, dy, dz, cell, wt);
-#pragma unroll
-  for (int d = 0; d < MAXD; ++d) beta[d] = 0.0f;
-  const int D = c.D;
+  // all loads first (independent), then the blend
+  float4 v[4][NQ];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const float *bp = c.beta + (size_t)cell[q] * D;
+    const float4 *bp = reinterpret_cast<const float4 *>(c.beta) + (size_t)cell[q] * c.bq;
 #pragma unroll
-    for (int d = 0; d < MAXD; ++d)
-      if (d < D) beta[d] = fmaf(wt[q], __ldg(bp + d), beta[d]);
+    for (int j = 0; j < NQ; ++j) v[q][j] = j < c.bq ? bp[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc.x = fmaf(wt[q], v[q][j].x, acc.x);
+      acc.y = fmaf(wt[q], v[q][j].y, acc.y);
+      acc.z = fmaf(wt[q], v[q][j].z, acc.z);
+      acc.w = fmaf(wt[q], v[q][j].w, acc.w);
+    }
+    beta[4 * j + 0] = acc.x;
+    beta[4 * j + 1] = acc.y;
+    beta[4 * j + 2] = acc.z;
+    beta[4 * j + 3] = acc.w;
   }
 }
 

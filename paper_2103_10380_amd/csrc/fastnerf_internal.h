@@ -11,6 +11,7 @@ struct fastnerf_cache_s {
   uint8_t *rec = nullptr;      // records, brick-linear, stride bytes each
   float *beta = nullptr;       // [l][l][D]
   uint32_t *occ = nullptr;     // occupancy bits
+  uint8_t *dist = nullptr;     // per-brick Chebyshev distance to the nearest occupied brick
   float *scales = nullptr;     // 1 + 3D
   unsigned *amax = nullptr;    // FP8 absmax accumulators (float bits)
   int stride = 0, payload = 0, rec_shift = 0, nchunk = 0;

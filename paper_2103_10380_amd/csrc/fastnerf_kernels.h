@@ -19,6 +19,11 @@ hipError_t launch_pack(int fmt, const float *sigma, const float *u, int z0, int 
                        const DevCache &c, hipStream_t s);
 hipError_t launch_occupancy(int fmt, const DevCache &c, int dilate, uint32_t *words,
                             hipStream_t s);
+// Per-brick distance field from the occupancy bits: dist[b] = Chebyshev
+// distance in bricks to the nearest occupied brick, capped at kDistCap. tmp
+// holds nbo^3 bytes of scratch.
+hipError_t launch_distance(const DevCache &c, const uint32_t *words, uint8_t *dist, uint8_t *tmp,
+                           hipStream_t s);
 hipError_t launch_readback(int fmt, const DevCache &c, float *sigma, float *u, hipStream_t s);
 hipError_t launch_lookup(int fmt, bool lin, const DevCache &c, int n, const float *pts,
                          const float *dirs, float *su, float *bo, hipStream_t s);

@@ -2,12 +2,14 @@
 //
 //   k_render      the hot path: rays of 8x8 pixel tiles (one tile per wave,
 //                 tiles taken from persistent queues), empty-space skipping on
-//                 the brick bitgrid, record gathers, Eq. 5 colour, Eq. 1
-//                 compositing in optical depth with early termination.
+//                 the brick bitgrid and distance field, record gathers, Eq. 5
+//                 colour, Eq. 1 compositing in optical depth with early
+//                 termination.
 //   k_render_step the same over a serving step's views and scenes.
 //   k_absmax      per-channel |max| for FP8 scales.
 //   k_pack        FP32 slab -> padded brick-linear records in the storage format.
 //   k_occupancy   brick bitgrid from the stored densities.
+//   k_dist_*      per-brick Chebyshev distance to the nearest occupied brick.
 //   k_readback    records -> FP32 arrays (test hook).
 //   k_lookup      the render kernel's own lookups at given points (test hook).
 #include "fastnerf_device.h"
@@ -50,12 +52,6 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
   const int px = (lt % V.tiles_x) * 8 + (lane & 7);
   const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
   if (px >= W || py >= H) return;
-  float sc[FMT == 3 ? kMaxCh : 1];
-  if (FMT == 3) {
-#pragma unroll
-    for (int j = 0; j < (FMT == 3 ? kMaxCh : 1); ++j)
-      sc[j] = j < 1 + 3 * c.D ? c.scales[j] : 0.0f;
-  }
   const int N = V.N;
   const int k = c.k;
   const float kf = c.kf;
@@ -91,8 +87,22 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
   }
   float tau = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
   if (t1 > t0) {
-    float beta[MAXD];
-    dir_lookup<MAXD>(c, (float)ddx, (float)ddy, (float)ddz, beta);
+    float cw[ColourWeights<FMT, MAXD>::n];
+    float s0 = 1.0f;
+    {
+      float beta[MAXD];
+      dir_lookup<MAXD>(c, (float)ddx, (float)ddy, (float)ddz, beta);
+#pragma unroll
+      for (int d = 0; d < MAXD; ++d) {
+        if (FMT == 3) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) cw[3 * d + ch] = beta[d] * c.scales[1 + 3 * d + ch];
+        } else {
+          cw[d] = beta[d];
+        }
+      }
+      if (FMT == 3) s0 = c.scales[0];
+    }
     const float dt = (float)((t1 - t0) / (double)N);
     // grid coordinates of the interval start and the per-distance step;
     // sample i sits at distance (i + 1/2) dt past the start
@@ -101,49 +111,63 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
     const float ogz = (float)((fma(t0, ddz, V.o[2]) - c.bmin[2]) * c.inv_h[2]);
     const float gdx = (float)(ddx * c.inv_h[0]), gdy = (float)(ddy * c.inv_h[1]),
                 gdz = (float)(ddz * c.inv_h[2]);
-    // Samples are taken in windows of kWin: the occupancy bits of a window are
-    // fetched with independent loads and one wait, then its occupied samples
-    // are gathered and composited in order, B records in flight at a time.
-    const bool skip = c.occ != nullptr;
+    // Samples are taken in windows of kWin: the occupancy bits of a window
+    // are fetched with independent loads and one wait, then its occupied
+    // samples are gathered and composited in order, B records in flight at a
+    // time. With the same wait, the brick distance d of the window's last
+    // sample is read: d >= 2 (bricks, max norm, to the nearest occupied brick)
+    // proves that every point within (d - 1) brick edges of that sample lies
+    // in an empty brick, so the next window starts past the last sample so
+    // proven empty. Samples advance vstep voxels each in the max norm; half a
+    // voxel of margin covers FP32 position rounding.
+    const float vstep = dt * fmaxf(fabsf(gdx), fmaxf(fabsf(gdy), fabsf(gdz)));
+    const float inv_step = 1.0f / vstep;
+    const float bedge = (float)(1 << c.oshift);
     int i = 0;
     bool alive = true;
     while (alive) {
       uint32_t mask = 0u;
+      int next = i + kWin;
       {
-        uint32_t word[kWin], bitpos[kWin];
+        // a cache without a bitgrid has one all-ones word and one zero
+        // distance, with oshift past every coordinate bit
+        uint32_t word[kWin], bitpos[kWin], dlast = 0u;
         bool in[kWin];
 #pragma unroll
         for (int j = 0; j < kWin; ++j) {
           const float t = ((float)(i + j) + 0.5f) * dt;
           const float gx = fmaf(t, gdx, ogx), gy = fmaf(t, gdy, ogy), gz = fmaf(t, gdz, ogz);
-          in[j] = (i + j < N) && gx >= 0.0f && gx <= kf && gy >= 0.0f && gy <= kf &&
-                  gz >= 0.0f && gz <= kf;
-          word[j] = ~0u;
-          bitpos[j] = 0u;
-          if (skip) {  // clamped voxel: always a valid address, even when not inside
-            const int x = min(max((int)(gx + kTie), 0), k - 1),
-                      y = min(max((int)(gy + kTie), 0), k - 1),
-                      z = min(max((int)(gz + kTie), 0), k - 1);
-            const uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo +
-                                  (uint32_t)(y >> c.oshift)) * (uint32_t)c.nbo +
-                                 (uint32_t)(x >> c.oshift);
-            word[j] = __ldg(c.occ + (bit >> 5));
-            bitpos[j] = bit & 31u;
-          }
+          // inside the box: 0 <= g <= k on every axis
+          in[j] = (i + j < N) && fminf(fminf(gx, gy), gz) >= 0.0f &&
+                  fmaxf(fmaxf(gx, gy), gz) <= kf;
+          // clamped voxel: always a valid address, even when not inside
+          const int x = min(max((int)(gx + kTie), 0), k - 1),
+                    y = min(max((int)(gy + kTie), 0), k - 1),
+                    z = min(max((int)(gz + kTie), 0), k - 1);
+          const uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo +
+                                (uint32_t)(y >> c.oshift)) * (uint32_t)c.nbo +
+                               (uint32_t)(x >> c.oshift);
+          word[j] = __ldg(c.occ + (bit >> 5));
+          bitpos[j] = bit & 31u;
+          if (j == kWin - 1) dlast = __ldg(c.dist + bit);
         }
 #pragma unroll
         for (int j = 0; j < kWin; ++j)
           mask |= (uint32_t)(in[j] && ((word[j] >> bitpos[j]) & 1u)) << j;
+        if (dlast >= 2u) {
+          const float run = fminf(((float)(dlast - 1u) * bedge - 0.5f) * inv_step, (float)N);
+          next += (int)run;
+        }
       }
       while (mask != 0u && alive) {
+        // the next B occupied samples; slots past the last one repeat the
+        // first sample's voxel, so every load has a valid (cached) address
         int vx[B], vy[B], vz[B];
         float wx[B], wy[B], wz[B];
         bool have[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
           have[b] = mask != 0u;
-          vx[b] = vy[b] = vz[b] = 0;
-          wx[b] = wy[b] = wz[b] = 0.0f;
           if (have[b]) {
             const int j = __builtin_ctz(mask);
             mask &= mask - 1u;
@@ -162,27 +186,41 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
               vx[b] = min((int)(gx + kTie), k - 1);
               vy[b] = min((int)(gy + kTie), k - 1);
               vz[b] = min((int)(gz + kTie), k - 1);
+              wx[b] = wy[b] = wz[b] = 0.0f;
             }
+          } else {
+            vx[b] = vx[0];
+            vy[b] = vy[0];
+            vz[b] = vz[0];
+            wx[b] = wy[b] = wz[b] = 0.0f;
           }
         }
         if (!LIN) {
+          uint64_t off[B];
+#pragma unroll
+          for (int b = 0; b < B; ++b) off[b] = record_offset(c, vx[b], vy[b], vz[b]);
           uint32_t w[B][RW::nwords];
 #pragma unroll
-          for (int b = 0; b < B; ++b)
-            if (have[b]) load_record<FMT, MAXD>(c, record_offset(c, vx[b], vy[b], vz[b]), w[b]);
+          for (int b = 0; b < B; ++b) load_record<FMT, MAXD>(c, off[b], w[b]);
+          // branch-free, so that all B records are requested before the first
+          // is used: an unused slot (past the window's last occupied sample,
+          // or after the stop) adds zero optical depth and zero colour
 #pragma unroll
           for (int b = 0; b < B; ++b) {
-            if (!have[b] || !alive) continue;
-            const float s = rec_sigma<FMT>(w[b], sc);
+            // no contraction of sigma*dt into the optical-depth sum: every
+            // slot, and every occupancy setting, rounds alike
+#pragma clang fp contract(off)
+            const bool use = have[b] && alive;
+            const float s = rec_sigma<FMT>(w[b], s0);
             float r, g, bl;
-            rec_colour<FMT, MAXD>(w[b], beta, sc, r, g, bl);
-            const float sd = s * dt;
+            rec_colour<FMT, MAXD>(w[b], cw, r, g, bl);
+            const float sd = use ? s * dt : 0.0f;
             const float wgt = expf(-tau) * -expm1f(-sd);
             cr = fmaf(wgt, r, cr);
             cg = fmaf(wgt, g, cg);
             cb = fmaf(wgt, bl, cb);
-            tau += sd;
-            if (tau > V.lim) alive = false;  // every later sample would be stopped
+            tau = tau + sd;
+            alive = alive && !(tau > V.lim);  // every later sample would be stopped
           }
         } else {
 #pragma unroll
@@ -203,8 +241,8 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
                                (((q >> 1) & 1) ? wy[b] : 1.0f - wy[b]) *
                                (((q >> 2) & 1) ? wz[b] : 1.0f - wz[b]);
               float rq, gq, bq;
-              rec_colour<FMT, MAXD>(w[q], beta, sc, rq, gq, bq);
-              s = fmaf(wq, rec_sigma<FMT>(w[q], sc), s);
+              rec_colour<FMT, MAXD>(w[q], cw, rq, gq, bq);
+              s = fmaf(wq, rec_sigma<FMT>(w[q], s0), s);
               r = fmaf(wq, rq, r);
               g = fmaf(wq, gq, g);
               bl = fmaf(wq, bq, bl);
@@ -214,12 +252,12 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
             cr = fmaf(wgt, r, cr);
             cg = fmaf(wgt, g, cg);
             cb = fmaf(wgt, bl, cb);
-            tau += sd;
+            tau = tau + sd;
             if (tau > V.lim) alive = false;
           }
         }
       }
-      i += kWin;
+      i = next;
       if (i >= N) alive = false;
     }
   }
@@ -460,6 +498,35 @@ __global__ void k_occupancy(DevCache c, int dilate, uint32_t *__restrict__ words
   }
 }
 
+// Brick distance field, step 1: 0 for occupied bricks, kDistCap otherwise.
+__global__ void k_dist_init(const uint32_t *__restrict__ words, int64_t nbr,
+                            uint8_t *__restrict__ out) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nbr;
+       b += (int64_t)gridDim.x * blockDim.x)
+    out[b] = ((words[b >> 5] >> (b & 31)) & 1u) ? 0 : kDistCap;
+}
+
+// One axis of the Chebyshev (max-norm) distance transform, which separates:
+// out(i) = min over |i - j| <= kDistCap of max(|i - j|, in(j)) along the axis.
+// Applied along x, y and z in turn to the step-1 field it yields, for every
+// brick, min(kDistCap, max-norm distance in bricks to the nearest occupied one).
+__global__ void k_dist_axis(const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int nb,
+                            int axis) {
+  const int64_t nbr = (int64_t)nb * nb * nb;
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nb : (int64_t)nb * nb);
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nbr;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)((b / stride) % nb);
+    const int64_t base = b - (int64_t)i * stride;
+    int best = in[b];
+    for (int dd = 1; dd < best; ++dd) {  // offsets >= best cannot lower it
+      if (i - dd >= 0) best = min(best, max(dd, (int)in[base + (int64_t)(i - dd) * stride]));
+      if (i + dd < nb) best = min(best, max(dd, (int)in[base + (int64_t)(i + dd) * stride]));
+    }
+    out[b] = (uint8_t)best;
+  }
+}
+
 template <int FMT, int MAXD>
 __global__ void k_readback(DevCache c, float *__restrict__ sigma, float *__restrict__ u) {
   using RW = RecWords<FMT, MAXD>;
@@ -605,27 +672,42 @@ hipError_t launch_readback_f(const DevCache &c, float *sigma, float *u, hipStrea
 
 }  // namespace
 
-hipError_t launch_render_step(bool lin, int D, const RenderArgs &a, int grid, hipStream_t s) {
-  if (D <= 8) {
-    if (lin) hipLaunchKernelGGL((k_render_step<8, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_render_step<8, false>), dim3(grid), dim3(kBlock), 0, s, a);
-  } else {
-    if (lin) hipLaunchKernelGGL((k_render_step<16, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_render_step<16, false>), dim3(grid), dim3(kBlock), 0, s, a);
-  }
+namespace {
+
+template <int MAXD>
+hipError_t launch_step_t(bool lin, const RenderArgs &a, int grid, hipStream_t s) {
+  if (lin) hipLaunchKernelGGL((k_render_step<MAXD, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_render_step<MAXD, false>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-int render_step_occupancy(bool lin, int D) {
+template <int MAXD>
+int step_occupancy_t(bool lin) {
   int nb = 0;
-  hipError_t e;
-  if (D <= 8)
-    e = lin ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<8, true>, kBlock, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<8, false>, kBlock, 0);
-  else
-    e = lin ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<16, true>, kBlock, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<16, false>, kBlock, 0);
+  const hipError_t e =
+      lin ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<MAXD, true>, kBlock, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<MAXD, false>, kBlock, 0);
   return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+}  // namespace
+
+// D selects the kernel's component-count class (maxd_class), which must be the
+// class of every cache of the step.
+hipError_t launch_render_step(bool lin, int D, const RenderArgs &a, int grid, hipStream_t s) {
+  switch (maxd_class(D)) {
+    case 4: return launch_step_t<4>(lin, a, grid, s);
+    case 8: return launch_step_t<8>(lin, a, grid, s);
+    default: return launch_step_t<16>(lin, a, grid, s);
+  }
+}
+
+int render_step_occupancy(bool lin, int D) {
+  switch (maxd_class(D)) {
+    case 4: return step_occupancy_t<4>(lin);
+    case 8: return step_occupancy_t<8>(lin);
+    default: return step_occupancy_t<16>(lin);
+  }
 }
 
 int render_occupancy(int fmt, bool lin, int D) {
@@ -676,6 +758,19 @@ hipError_t launch_occupancy(int fmt, const DevCache &c, int dilate, uint32_t *wo
     case 2: hipLaunchKernelGGL(k_occupancy<2>, dim3(grid), dim3(kBlock), 0, s, c, dilate, words); break;
     default: hipLaunchKernelGGL(k_occupancy<3>, dim3(grid), dim3(kBlock), 0, s, c, dilate, words); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_distance(const DevCache &c, const uint32_t *words, uint8_t *dist, uint8_t *tmp,
+                           hipStream_t s) {
+  const int nb = c.nbo;
+  const int64_t nbr = (int64_t)nb * nb * nb;
+  int64_t blocks = (nbr + kBlock - 1) / kBlock;
+  const int grid = (int)(blocks < 65536 ? (blocks < 1 ? 1 : blocks) : 65536);
+  hipLaunchKernelGGL(k_dist_init, dim3(grid), dim3(kBlock), 0, s, words, nbr, tmp);
+  hipLaunchKernelGGL(k_dist_axis, dim3(grid), dim3(kBlock), 0, s, tmp, dist, nb, 0);
+  hipLaunchKernelGGL(k_dist_axis, dim3(grid), dim3(kBlock), 0, s, dist, tmp, nb, 1);
+  hipLaunchKernelGGL(k_dist_axis, dim3(grid), dim3(kBlock), 0, s, tmp, dist, nb, 2);
   return hipGetLastError();
 }
 

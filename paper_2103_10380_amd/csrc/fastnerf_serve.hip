@@ -102,8 +102,9 @@ class GpuExecutor : public fs::Executor {
     hipGraphExec_t exec = nullptr;
   };
 
+  // (interpolation, component-count class): the class fixes the record layout
   static int group_key(const fastnerf_cache_s *c) {
-    return (c->desc.pos_interp == FASTNERF_LINEAR ? 2 : 0) + (c->desc.D <= 8 ? 0 : 1);
+    return (c->desc.pos_interp == FASTNERF_LINEAR ? 4 : 0) + maxd_class(c->desc.D) / 8;
   }
 
   fastnerf_status group(int key, Group **out) {
@@ -118,8 +119,8 @@ class GpuExecutor : public fs::Executor {
     HIP_CHECK(hipMalloc(&g->d_table, table_bytes_));
     HIP_CHECK(hipMalloc(&g->counter, kQueueCounters * sizeof(unsigned)));
     HIP_CHECK(hipMemset(g->counter, 0, kQueueCounters * sizeof(unsigned)));
-    const bool lin = key & 2;
-    const int D = (key & 1) ? 16 : 8;
+    const bool lin = key & 4;
+    const int D = (key & 3) == 0 ? 4 : ((key & 3) == 1 ? 8 : 16);
     const int grid = cus_ * render_step_occupancy(lin, D);
     RenderArgs a;
     memset(&a, 0, sizeof a);

@@ -91,3 +91,48 @@ def test_linearity_in_radiance():
     lhs, a, b = r(mix), r(u), r(u2)
     np.testing.assert_allclose(lhs[:, :3], 0.5 * a[:, :3] - 0.25 * b[:, :3], atol=2e-6)
     assert np.array_equal(lhs[:, 3], a[:, 3])
+
+
+def test_skip_distance_is_chessboard_distance():
+    """The per-brick skip distance equals scipy's chessboard distance transform
+    of the occupancy bitgrid, capped at 63 (library routine)."""
+    from scipy import ndimage
+    sig, u, beta = G.config1_scene()
+    for brick, lin in ((8, False), (4, True), (16, False)):
+        cache = G.make_cache(sig, u, beta, pos_linear=lin, brick=brick)
+        occ = cache.occupancy()
+        dist = cache.skip_distance()
+        assert occ.any() and not occ.all()
+        ref = np.minimum(ndimage.distance_transform_cdt(~occ, metric="chessboard"), 63)
+        assert np.array_equal(dist, ref)
+    assert G.make_cache(sig, u, beta, brick=0).skip_distance().size == 0
+
+
+@pytest.mark.parametrize("storage", ["f32", "fp8"])
+def test_distance_skipping_is_exact_paper_like(storage):
+    """A k=256 scene of the paper-scale generator (sparse, thin shells), samples
+    in the box: renders with skipping over 4-, 8- and 16-voxel bricks equal the
+    render without an occupancy grid, bitwise, on orbit views."""
+    import paper_2103_10380_amd as fn
+    import torch
+    spec = synth.paper_scene_spec(k=256)
+    p = synth.draw(spec)
+    beta = synth.beta_table(p)
+    caches = []
+    for brick in (0, 4, 8, 16):
+        desc = fn.make_desc(spec.k, spec.D, spec.l, storage=storage, brick=brick,
+                            sample_mode=fn.IN_BOX)
+        c = fn.Cache.create_empty(desc, beta)
+        for phase in ("scan", "upload") if storage == "fp8" else ("upload",):
+            for z0 in range(0, spec.k, 32):
+                sg = synth.density(p, z0, 32, "cuda")
+                uu = synth.radiance(p, z0, 32, "cuda")
+                (c.scan_slab if phase == "scan" else c.upload_slab)(z0, sg, uu)
+        c.finalize()
+        caches.append(c)
+    for v in synth.paper_orbit(5, W=160, H=144):
+        outs = [G.render_gpu(c, v, 192, 1e-4) for c in caches]
+        assert (outs[0][:, 3] > 0).mean() > 0.05
+        for o in outs[1:]:
+            assert np.array_equal(outs[0], o)
+    torch.cuda.synchronize()
