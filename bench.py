@@ -91,7 +91,9 @@ def build_caches(spec, storages, want_sparse, device):
     return p, beta, caches, sparse, occ_vox / k ** 3
 
 
-def time_orbit(fn, cache, views, N, eps, steps, warmup):
+def time_single(fn, cache, views, N, eps, steps, warmup):
+    """Per-frame latency: every view in a launch of its own, HIP events around
+    each launch on the launch stream."""
     import torch
     outs = [torch.empty((v.H, v.W, 4), dtype=torch.float32, device="cuda") for v in views]
     for _ in range(warmup):
@@ -100,7 +102,6 @@ def time_orbit(fn, cache, views, N, eps, steps, warmup):
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps * len(views))]
-    t0 = time.perf_counter()
     q = 0
     for _ in range(steps):
         for v, o in zip(views, outs):
@@ -109,9 +110,28 @@ def time_orbit(fn, cache, views, N, eps, steps, warmup):
             evs[q][1].record()
             q += 1
     torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in evs])
+
+
+def time_batched(fn, cache, views, N, eps, steps, warmup):
+    """Throughput: one step renders every view of the orbit in one persistent
+    launch; the wall clock brackets exactly `steps` steps, with a device
+    synchronisation on both sides, and HIP events time every launch."""
+    import torch
+    outs = [torch.empty((v.H, v.W, 4), dtype=torch.float32, device="cuda") for v in views]
+    for _ in range(warmup):
+        fn.render_batch(cache, views, N, eps, outs=outs)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        fn.render_batch(cache, views, N, eps, outs=outs)
+        b.record()
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    frame_ms = np.array([a.elapsed_time(b) for a, b in evs])
-    return wall, frame_ms, outs
+    return wall, np.array([a.elapsed_time(b) for a, b in evs]), outs
 
 
 def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs, seed=11):
@@ -157,6 +177,177 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs
         if t_cpu >= seconds:
             break
     return rays, t_cpu, nviews, totals, f32, other
+
+
+def time_launches(fn_launch, reps, warmup):
+    """Mean and per-launch durations (ms) of fn_launch() with events on the
+    current stream, after warmup launches."""
+    import torch
+    for _ in range(warmup):
+        fn_launch()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn_launch()
+        b.record()
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in evs])
+
+
+def precision_sweep(fn, reps=20):
+    """The plain scene (k=128, D=8, l=64, 6 ellipsoids, seed 0) on an 8-view
+    orbit at r=3, el=0.4 (200x200, samples in [2, 4], N=128, eps=1e-4), with the
+    position cache stored FP32 / FP16 / BF16 / FP8-E4M3, accumulation in FP32:
+    error against the FP64 oracle on the FP32 inputs, Mrays/s and the
+    algorithmic GB/s (this cache fits the last-level cache, so the rate is not
+    an HBM rate)."""
+    import oracle
+    import synth
+    sig, u, beta, _ = synth.scene_arrays(synth.plain_scene_spec())
+    views = [synth.orbit_view(3.0, 2 * np.pi * v / 8 + 0.7, 0.4, 200, 200, 2.0, 4.0)
+             for v in range(8)]
+    N, eps = 128, 1e-4
+    sc = oracle.Scene(beta, sig, u, occ_brick=8)
+    ref, totals = [], dict(hit=0, occ_samples=0, rays=0)
+    for v in views:
+        r = oracle.render(sc, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps,
+                          tol=oracle.DEFAULT_TOL)
+        ref.append(r)
+        for key in totals:
+            totals[key] += r["counts"][key]
+    out = {}
+    for st in ("f32", "f16", "bf16", "fp8"):
+        cache = fn.Cache.create(fn.make_desc(128, 8, 64, storage=st, brick=8), sig, u, beta)
+        stride, payload = cache.record_bytes
+        import torch
+        outs = [torch.empty((v.H, v.W, 4), dtype=torch.float32, device="cuda") for v in views]
+
+        def orbit():
+            for v, o in zip(views, outs):
+                fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, out=o)
+        ms = time_launches(orbit, reps, 3)
+        errs, se, n, se_hit, n_hit = [], 0.0, 0, 0.0, 0
+        for o, res in zip(outs, ref):
+            g = o.reshape(-1, 4).cpu().numpy().astype(np.float64)
+            # max-abs against the nearest admissible oracle result (voxel-face
+            # and stop-point ties); PSNR against the oracle's primary result
+            err, _ = oracle.matches(g, res, 1.0)
+            errs.append(float(err.max()))
+            r = res["rgba"]
+            d2 = (g[:, :3] - r[:, :3]) ** 2
+            se += d2.sum()
+            n += d2.size
+            hit = r[:, 3] > 0.01
+            se_hit += d2[hit].sum()
+            n_hit += d2[hit].size
+        rays = sum(v.H * v.W for v in views)
+        alg = totals["occ_samples"] * payload + totals["hit"] * 4 * 8 * 4 + rays * 16
+        psnr = lambda e, m: float("inf") if e == 0 else 10 * np.log10(m / e)
+        out[st] = {"max_abs_err": float(max(errs)), "psnr_db": round(psnr(se, n), 3),
+                   "psnr_hit_db": round(psnr(se_hit, n_hit), 3),
+                   "mrays_per_s": round(rays / (float(np.mean(ms)) / 1e3) / 1e6, 1),
+                   "alg_gb_per_s": round(alg / (float(np.mean(ms)) / 1e3) / 1e9, 1)}
+        cache.destroy()
+    return out
+
+
+def batched_uneven(fn, reps=10):
+    """64 views of the plain scene in one launch: resolutions drawn from
+    {256^2, 512^2, 800^2, 1024^2, 1280x720}, radii U[3,5], elevations U[-1,1]
+    (seed 2); trilinear position lookup, FP16 cache, samples in the box,
+    N=128, eps=1e-4."""
+    import torch
+    import synth
+    sig, u, beta, _ = synth.scene_arrays(synth.plain_scene_spec())
+    cache = fn.Cache.create(fn.make_desc(128, 8, 64, storage="f16", pos_interp=fn.LINEAR,
+                                         brick=8, sample_mode=fn.IN_BOX), sig, u, beta)
+    views = synth.random_views(64, 2, [(256, 256), (512, 512), (800, 800), (1024, 1024),
+                                       (1280, 720)], (3.0, 5.0), (-1.0, 1.0), 0.0, 100.0)
+    outs = [torch.empty((v.H, v.W, 4), dtype=torch.float32, device="cuda") for v in views]
+    ms = time_launches(lambda: fn.render_batch(cache, views, 128, 1e-4, outs=outs), reps, 2)
+    rays = sum(v.H * v.W for v in views)
+    cache.destroy()
+    return {"views": 64, "rays_per_launch": rays, "launch_ms_mean": round(float(np.mean(ms)), 4),
+            "launch_ms_p50": round(float(np.percentile(ms, 50)), 4),
+            "mrays_per_s": round(rays / (float(np.mean(ms)) / 1e3) / 1e6, 1)}
+
+
+SERVE_RES = [(400, 400), (800, 800), (1280, 720), (1920, 1080)]
+
+
+def serve_poisson(fn, caches, lam, n_req, n_warm, seed=3, N=192, eps=1e-4):
+    """Poisson arrivals at lam requests/s over the resident caches: each request
+    draws a scene, a resolution from SERVE_RES and a pose (r U[3,5], az U[0,2pi),
+    el U[-1,1]); a waiter thread collects results in submission order.
+    Latency is the server's (submission to completion)."""
+    import threading
+    import queue
+    import synth
+    rng = np.random.default_rng(seed)
+    srv = fn.Server(caches, arena_bytes=4 << 30, max_inflight=32)
+    q = queue.Queue()
+    lat, rays_done, done_t = [], [0], [0.0]
+
+    def waiter():
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            tk, nr, measured = item
+            _, ms = srv.wait(tk)
+            srv.release(tk)
+            if measured:
+                lat.append(ms)
+                rays_done[0] += nr
+                done_t[0] = time.perf_counter()
+    th = threading.Thread(target=waiter)
+    th.start()
+    rejected = 0
+    t_next = time.perf_counter()
+    t_first = None
+    for i in range(n_warm + n_req):
+        t_next += rng.exponential(1.0 / lam)
+        W, H = SERVE_RES[rng.integers(len(SERVE_RES))]
+        v = synth.orbit_view(rng.uniform(3.0, 5.0), rng.uniform(0, 2 * np.pi),
+                             rng.uniform(-1.0, 1.0), W, H, 0.0, 100.0)
+        scene = int(rng.integers(len(caches)))
+        while time.perf_counter() < t_next:
+            time.sleep(max(0.0, min(0.0005, t_next - time.perf_counter())))
+        if i == n_warm:
+            t_first = time.perf_counter()
+        try:
+            tk = srv.submit(scene, v.K, v.c2w, H, W, v.near, v.far, N, eps)
+        except fn.FastNeRFError:
+            rejected += 1
+            continue
+        q.put((tk, W * H, i >= n_warm))
+    q.put(None)
+    th.join()
+    st = srv.stats()
+    srv.destroy()
+    el = done_t[0] - t_first
+    lat = np.array(lat)
+    return {"lambda_req_per_s": lam, "requests": int(len(lat)), "rejected": rejected,
+            "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+            "frames_per_s": round(len(lat) / el, 1),
+            "mrays_per_s": round(rays_done[0] / el / 1e6, 1),
+            "server_steps": st["steps"], "max_requests_per_step": st["max_batch"]}
+
+
+def serving_scenes(fn):
+    """The four resident serving scenes: k=512 FP16 (seed 10), k=512 FP8 (11),
+    k=768 FP16 (12), k=768 FP8 (13); paper-scale generator, D=8, l=384."""
+    import synth
+    caches = []
+    for k, st, seed in ((512, "f16", 10), (512, "fp8", 11), (768, "f16", 12), (768, "fp8", 13)):
+        spec = synth.paper_scene_spec(k=k, seed=seed)
+        _, _, cs, _, occ = build_caches(spec, [st], False, "cuda")
+        log(f"serving scene k={k} {st} seed {seed}: occupancy {occ:.4f}")
+        caches.append(cs[st])
+    return caches
 
 
 def summarize_profile(paths, match=("k_render", "neg_kernel")):
@@ -244,6 +435,14 @@ def main():
                     help="also run a plain 1 GiB device copy (scale for profiler byte counters)")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DIR",
                     help="print a summary of rocprofv3 CSV output directories and exit")
+    ap.add_argument("--serving", action="store_true",
+                    help="only the serving workload: four resident scenes, Poisson arrivals "
+                         "at 50/100/200/400/1600/6400 requests/s (one JSON line)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-view latency launches (profiling runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision sweep, the batched launch and the serving sample")
     ap.add_argument("--pmc-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the render kernel's calibrated HBM bytes per launch (JSON) "
                          "from FETCH_SIZE and WRITE_SIZE runs made with --calibrate-copy")
@@ -266,6 +465,27 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fn.lib()
 
+    if args.serving:
+        t0 = time.perf_counter()
+        caches = serving_scenes(fn)
+        log(f"serving scenes built in {time.perf_counter() - t0:.1f}s")
+        rows = []
+        for lam in (50, 100, 200, 400, 1600, 6400):
+            r = serve_poisson(fn, caches, lam, args.serve_requests, 100)
+            log(f"lambda {lam}: p50 {r['latency_ms_p50']} ms p99 {r['latency_ms_p99']} ms, "
+                f"{r['frames_per_s']} frames/s")
+            rows.append(r)
+        print(json.dumps({
+            "metric": "serving latency (p50/p99) under Poisson arrivals", "unit": "ms",
+            "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "4 resident scenes (k=512 FP16 seed 10, k=512 FP8 seed 11, "
+                                   "k=768 FP16 seed 12, k=768 FP8 seed 13; D=8, l=384), "
+                                   "requests of 400^2/800^2/1280x720/1920x1080 at random "
+                                   "poses, N=192 in the box, eps=1e-4, seed 3",
+                       "warmup_requests": 100, "requests_per_rate": args.serve_requests},
+            "rates": rows, "kernel_digest": kernel_digest()}), flush=True)
+        return
+
     N, eps = 192, 1e-4
     spec = synth.paper_scene_spec(k=args.k)
     views = synth.paper_orbit(args.views)
@@ -282,15 +502,19 @@ def main():
     results = {}
     outs_f32 = None
     for st in storages:
-        wall, frame_ms, outs = time_orbit(fn, caches[st], views, N, eps, args.steps,
-                                          args.warmup)
+        wall, step_ms, outs = time_batched(fn, caches[st], views, N, eps, args.steps,
+                                           args.warmup)
+        frame_ms = (np.array([0.0]) if args.no_single else
+                    time_single(fn, caches[st], views, N, eps, args.steps, args.warmup))
         rays = args.steps * sum(v.H * v.W for v in views)
-        results[st] = dict(wall=wall, frame_ms=frame_ms, mrays=rays / wall / 1e6)
+        results[st] = dict(wall=wall, step_ms=step_ms, frame_ms=frame_ms,
+                           mrays=rays / wall / 1e6)
         if st == "f32":
             outs_f32 = outs
         else:
             results[st]["outs"] = outs
-        log(f"{st}: {results[st]['mrays']:.1f} Mrays/s, frame p50 "
+        log(f"{st}: {results[st]['mrays']:.1f} Mrays/s ({len(views)} views per launch, "
+            f"{np.mean(step_ms):.3f} ms per launch); single-view frame p50 "
             f"{np.percentile(frame_ms, 50):.3f} ms p99 {np.percentile(frame_ms, 99):.3f} ms")
 
     if args.calibrate_copy:
@@ -304,6 +528,7 @@ def main():
 
     r32 = results["f32"]
     frame_ms = r32["frame_ms"]
+    nv = len(views)
     line = {
         "metric": "Mrays/s at 800x800, cached render (paper-scale cache, FP32)",
         "value": round(r32["mrays"], 2),
@@ -323,12 +548,17 @@ def main():
                          "(28 ellipsoids + 12 shells, seed 1), "
                          f"{args.views}-view orbit r=4 el=0.5 at 800x800, N=192 samples in "
                          "the box, eps=1e-4, nearest position / bilinear direction lookup, "
-                         "8^3 occupancy bricks, FP32 cache"),
+                         "8^3 occupancy bricks, FP32 cache; one step = the whole orbit in one "
+                         "persistent launch"),
             "views_per_step": args.views, "width": 800, "height": 800, "N": N,
         },
-        "fps": round(1e3 / float(np.mean(frame_ms)), 1),
-        "frame_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
-        "frame_ms_p99": round(float(np.percentile(frame_ms, 99)), 4),
+        "fps": round(nv * args.steps / r32["wall"], 1),
+        "launch_ms_mean": round(float(np.mean(r32["step_ms"])), 4),
+        "single_view": None if args.no_single else {
+            "fps": round(1e3 / float(np.mean(frame_ms)), 1),
+            "frame_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
+            "frame_ms_p99": round(float(np.percentile(frame_ms, 99)), 4),
+            "note": "each view in a launch of its own; HIP events per launch"},
     }
 
     # ---------------------------------------------------------------- oracle leg
@@ -365,7 +595,8 @@ def main():
         D = spec.D
         alg_bytes = units["occ_samples"] * payload + units["hit_rays"] * 4 * D * 4 + \
             units["rays"] * 16
-        avg_s = float(np.mean(frame_ms)) / 1e3
+        alg_bytes *= nv  # the launch renders every view of the step
+        avg_s = float(np.mean(r32["step_ms"])) / 1e3
         achieved = alg_bytes / avg_s / 1e9
         traffic = None
         if os.path.exists(PMC_SUMMARY):
@@ -375,7 +606,7 @@ def main():
         line["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                            "kernel": "k_render<FP32, D<=8, nearest>",
+                            "kernel": f"k_render<FP32, D<=8, nearest>, {nv} views per launch",
                             "algorithmic_bytes_per_launch": round(alg_bytes),
                             "occupied_samples_per_launch": round(units["occ_samples"]),
                             "record_payload_bytes": payload, "record_stride_bytes": stride}
@@ -383,13 +614,30 @@ def main():
     for st in storages:
         r = results[st]
         variants[st] = {"mrays_per_s": round(r["mrays"], 2),
-                        "fps": round(1e3 / float(np.mean(r["frame_ms"])), 1),
-                        "frame_ms_p50": round(float(np.percentile(r["frame_ms"], 50)), 4),
-                        "frame_ms_p99": round(float(np.percentile(r["frame_ms"], 99)), 4),
+                        "fps": round(nv * args.steps / r["wall"], 1),
+                        "launch_ms_mean": round(float(np.mean(r["step_ms"])), 4),
+                        "single_view_frame_ms_p50": None if args.no_single else
+                        round(float(np.percentile(r["frame_ms"], 50)), 4),
+                        "single_view_frame_ms_p99": None if args.no_single else
+                        round(float(np.percentile(r["frame_ms"], 99)), 4),
                         "speedup_vs_f32": round(r["mrays"] / r32["mrays"], 3)}
         if not args.no_cpu and st != "f32":
             variants[st].update({k2: round(v2, 6) for k2, v2 in psnr_in[st].items()})
     line["variants"] = variants
+    if not args.no_extras:
+        if "f16" in caches and "fp8" in caches:
+            # continuous batching over the two reduced-precision caches already resident
+            r = serve_poisson(fn, [caches["f16"], caches["fp8"]], 200, 300, 30)
+            r["scenes"] = "paper-scale k=768 FP16 and FP8 caches of this run"
+            line["serving_sample"] = r
+            log(f"serving sample: p50 {r['latency_ms_p50']} ms p99 {r['latency_ms_p99']} ms")
+        for c in caches.values():
+            c.destroy()
+        caches = {}
+        line["batched_uneven"] = batched_uneven(fn)
+        log(f"batched uneven: {line['batched_uneven']}")
+        line["precision_sweep"] = precision_sweep(fn)
+        log(f"precision sweep: {line['precision_sweep']}")
     line["kernel_digest"] = kernel_digest()
     print(json.dumps(line), flush=True)
 
