@@ -109,13 +109,13 @@ template <> struct Fmt<2> {  // BF16
 
 template <> struct Fmt<3> {  // OCP E4M3 code; the caller multiplies by the channel scale
   static constexpr int bytes = 1;
-  // An E4M3 code e.mmm with bias 7 maps exactly onto binary16 with the same
-  // exponent/mantissa bits shifted into place (bias 15), scaled by 2^8; this
-  // holds for subnormal codes too. The NaN code is never stored (saturation).
+  // gfx950 converts OCP E4M3 pairs to FP32 in hardware (exact: every E4M3
+  // value is an FP32 value). The NaN code is never stored (saturation).
   __device__ static inline float get(const uint32_t *w, int j) {
-    uint32_t b = (w[j >> 2] >> ((j & 3) * 8)) & 0xFFu;
-    uint16_t h = (uint16_t)(((b & 0x80u) << 8) | ((b & 0x7Fu) << 7));
-    return (float)__builtin_bit_cast(_Float16, h) * 256.0f;
+    const int word = (int)w[j >> 2];
+    const auto v = (j & 2) ? __builtin_amdgcn_cvt_pk_f32_fp8(word, true)
+                           : __builtin_amdgcn_cvt_pk_f32_fp8(word, false);
+    return (j & 1) ? v[1] : v[0];
   }
 };
 
@@ -176,20 +176,38 @@ template <int FMT, int MAXD>
 __device__ inline void rec_colour(const uint32_t *w, const float *cw, float &r, float &g,
                                   float &b) {
   float cr = 0.f, cg = 0.f, cb = 0.f;
+  if constexpr (FMT == 3) {
+    // decode the record's codes two at a time
+    constexpr int NV = 1 + 3 * MAXD;
+    float v[(NV + 3) / 4 * 4];
+#pragma unroll
+    for (int q = 0; q < (NV + 3) / 4; ++q) {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[q], false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[q], true);
+      v[4 * q + 0] = lo[0];
+      v[4 * q + 1] = lo[1];
+      v[4 * q + 2] = hi[0];
+      v[4 * q + 3] = hi[1];
+    }
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+      cr = fmaf(cw[3 * d + 0], v[1 + 3 * d + 0], cr);
+      cg = fmaf(cw[3 * d + 1], v[1 + 3 * d + 1], cg);
+      cb = fmaf(cw[3 * d + 2], v[1 + 3 * d + 2], cb);
+    }
+    r = cr;
+    g = cg;
+    b = cb;
+    return;
+  }
 #pragma unroll
   for (int d = 0; d < MAXD; ++d) {
     const float ur = Fmt<FMT>::get(w, 1 + 3 * d + 0);
     const float ug = Fmt<FMT>::get(w, 1 + 3 * d + 1);
     const float ub = Fmt<FMT>::get(w, 1 + 3 * d + 2);
-    if (FMT == 3) {
-      cr = fmaf(cw[3 * d + 0], ur, cr);
-      cg = fmaf(cw[3 * d + 1], ug, cg);
-      cb = fmaf(cw[3 * d + 2], ub, cb);
-    } else {
-      cr = fmaf(cw[d], ur, cr);
-      cg = fmaf(cw[d], ug, cg);
-      cb = fmaf(cw[d], ub, cb);
-    }
+    cr = fmaf(cw[d], ur, cr);
+    cg = fmaf(cw[d], ug, cg);
+    cb = fmaf(cw[d], ub, cb);
   }
   r = cr;
   g = cg;

@@ -95,6 +95,30 @@ def test_readback_equals_oracle_quantiser(storage):
     assert np.array_equal(sc_g, sc_o)
 
 
+def test_fp8_every_code_decodes_exactly():
+    """Every finite E4M3 code, stored and read back: each of the 25 channels of
+    a k=8, D=8 cache cycles through all 254 finite codes and contains 448, so
+    its scale is exactly 1 and the stored code is the input's; the decoded
+    cache equals the OCP E4M3 value table (the oracle's decoder) bitwise."""
+    codes = [c for c in range(256) if c not in (0x7F, 0xFF)]
+    table = np.array([oracle.e4m3_decode(c) for c in codes], np.float32)
+    k, D, nch = 8, 8, 25
+    vals = np.empty((k ** 3, nch), np.float32)
+    for ch in range(nch):
+        vals[:, ch] = table[(np.arange(k ** 3) + 7 * ch) % len(codes)]
+        vals[ch, ch] = 448.0
+    sig = vals[:, 0].reshape(k, k, k).copy()
+    u = vals[:, 1:].reshape(k, k, k, D, 3).copy()
+    beta = np.full((4, 4, D), 1.0 / D, np.float32)
+    cache = G.make_cache(sig, u, beta, storage="fp8")
+    s_g, u_g, sc_g = cache.readback()
+    assert np.array_equal(sc_g, np.ones(nch, np.float32))
+    assert np.array_equal(s_g.cpu().numpy().reshape(-1), vals[:, 0])
+    assert np.array_equal(u_g.cpu().numpy().reshape(k ** 3, nch - 1), vals[:, 1:])
+    seen = set(np.unique(vals).tolist())
+    assert len(seen) == len(set(table.tolist()))  # every value, +-0 counted once
+
+
 @pytest.mark.parametrize("pos_linear", [False, True])
 @pytest.mark.parametrize("dir_linear", [False, True])
 def test_debug_lookup_matches_oracle(pos_linear, dir_linear):
