@@ -50,6 +50,14 @@
  *      faces: the nearest voxel of grid coordinate g is min(floor(g + 2^-9),
  *      k - 1) inside the box.
  *   R17 the transmittance sum of Eq. 1 runs over the samples before i.
+ *   R18 voxel traversal (N = 0): the rendering procedure of Sec. 4 visits every
+ *      voxel a ray crosses. The ray inside [near, far] intersected with the box
+ *      is cut at every crossing of a cell boundary (the R6b boundaries); each
+ *      piece is one sample, of length delta_i equal to the piece's length and
+ *      value that of the nearest voxel of its midpoint (nearest lookups only).
+ *      The nearest-lookup field is constant on each piece, so this evaluates
+ *      Eq. 1 exactly for the cached field, and the midpoint rule with N
+ *      samples converges to it as N grows.
  */
 #include "fastnerf_oracle.h"
 
@@ -292,6 +300,8 @@ typedef struct {
   int (*c)[3]; /* primary voxel coordinates per sample */
   double (*p)[3];
   double *t;
+  double *dl;  /* per-sample length (voxel traversal); unused with N samples */
+  int var_dl;  /* 1: use dl[i], 0: the constant spacing */
 } ray_work;
 
 static int work_reserve(ray_work *w, int n) {
@@ -299,10 +309,12 @@ static int work_reserve(ray_work *w, int n) {
   free(w->c);
   free(w->p);
   free(w->t);
+  free(w->dl);
   w->c = malloc(sizeof(int[3]) * (size_t)n);
   w->p = malloc(sizeof(double[3]) * (size_t)n);
   w->t = malloc(sizeof(double) * (size_t)n);
-  if (!w->c || !w->p || !w->t) return -1;
+  w->dl = malloc(sizeof(double) * (size_t)n);
+  if (!w->c || !w->p || !w->t || !w->dl) return -1;
   w->cap = n;
   return 0;
 }
@@ -311,6 +323,7 @@ static void work_free(ray_work *w) {
   free(w->c);
   free(w->p);
   free(w->t);
+  free(w->dl);
 }
 
 /* Alternative nearest-voxel coordinate across the nearest cell boundary (or
@@ -439,10 +452,11 @@ static void composite(const orc_scene *s, const orc_view *v, const orc_tol *tol,
       for (int d = 0; d < D; d++) acc += beta[d] * uu[3 * d + c];
       col[c] = acc;
     }
-    double alpha = -expm1(-sig * delta);
+    double dli = w->var_dl ? w->dl[i] : delta;
+    double alpha = -expm1(-sig * dli);
     double T = exp(-tau);
     for (int c = 0; c < 3; c++) C[c] += T * alpha * col[c];
-    tau += sig * delta;
+    tau += sig * dli;
     if (sig != 0.0) changed = 1;
   }
   if (changed) cand_push(cl, C, tau, s->bg);
@@ -489,6 +503,46 @@ static int place_samples(const orc_scene *s, const orc_view *v, const orc_tol *t
   return nch;
 }
 
+static int cmp_double(const void *a, const void *b) {
+  double x = *(const double *)a, y = *(const double *)b;
+  return x < y ? -1 : (x > y);
+}
+
+/* Voxel traversal (R18): cuts [t0, t1] at every crossing of an interior cell
+   boundary (grid coordinate i - ORC_TIE, R6b) and makes each piece of positive
+   length a sample at its midpoint, with the nearest voxel of the midpoint and
+   the piece's length. ts holds 3(k+1)+2 doubles. */
+static void place_segments(const orc_scene *s, const double o[3], const double d[3], double t0,
+                           double t1, double *ts, ray_work *w) {
+  int k = s->k, n = 0;
+  ts[n++] = t0;
+  for (int ax = 0; ax < 3; ax++) {
+    if (d[ax] == 0.0) continue;
+    double h = (s->bmax[ax] - s->bmin[ax]) / k;
+    for (int i = 1; i < k; i++) {
+      double t = (s->bmin[ax] + (i - ORC_TIE) * h - o[ax]) / d[ax];
+      if (t > t0 && t < t1) ts[n++] = t;
+    }
+  }
+  ts[n++] = t1;
+  qsort(ts, (size_t)n, sizeof(double), cmp_double);
+  w->n = 0;
+  w->var_dl = 1;
+  for (int q = 0; q + 1 < n; q++) {
+    double a = ts[q], b = ts[q + 1];
+    if (!(b > a)) continue;
+    double mid = 0.5 * (a + b);
+    int i = w->n;
+    w->t[i] = mid;
+    w->dl[i] = b - a;
+    for (int ax = 0; ax < 3; ax++) {
+      w->p[i][ax] = o[ax] + mid * d[ax];
+      w->c[i][ax] = nn_coord(grid_coord(s, ax, w->p[i][ax]), k);
+    }
+    w->n++;
+  }
+}
+
 static int dir_choices(const orc_scene *s, const orc_tol *tol, double th, double ph, int j,
                        int m, choice_t *ch, int nch) {
   if (s->dir_linear || !tol || tol->gamma_dir <= 0.0) return nch;
@@ -515,15 +569,17 @@ static int dir_choices(const orc_scene *s, const orc_tol *tol, double th, double
 }
 
 static void render_pixel(const orc_scene *s, const orc_view *v, const orc_tol *tol, int x,
-                         int y, ray_work *w, double rgba[4], cand_list *cl, int32_t *flag,
-                         orc_counts *cnt) {
+                         int y, ray_work *w, double *ts, double rgba[4], cand_list *cl,
+                         int32_t *flag, orc_counts *cnt) {
   double o[3], d[3], t0, t1;
   cl->n = 0;
   cl->overflow = 0;
   *flag = 0;
   orc_pixel_ray(v, x, y, o, d);
   if (cnt) cnt->rays++;
-  if (!orc_interval(s, v, o, d, &t0, &t1)) {
+  orc_scene clipped = *s; /* voxel traversal always stays inside the box (R18) */
+  clipped.in_box = 1;
+  if (!orc_interval(v->N == 0 ? &clipped : s, v, o, d, &t0, &t1)) {
     for (int c = 0; c < 3; c++) rgba[c] = s->bg[c];
     rgba[3] = 0.0;
     cand_push(cl, (double[3]){0, 0, 0}, 0.0, s->bg);
@@ -531,9 +587,16 @@ static void render_pixel(const orc_scene *s, const orc_view *v, const orc_tol *t
   }
   *flag |= ORC_HIT;
   if (cnt) cnt->hit++;
-  double delta = (t1 - t0) / v->N;
+  double delta = 0.0;
   choice_t ch[ORC_MAXCHOICE + 1];
-  int nch = place_samples(s, v, tol, o, d, t0, delta, w, ch);
+  int nch = 0;
+  if (v->N == 0) {
+    place_segments(s, o, d, t0, t1, ts, w);
+  } else {
+    delta = (t1 - t0) / v->N;
+    w->var_dl = 0;
+    nch = place_samples(s, v, tol, o, d, t0, delta, w, ch);
+  }
   double th, ph;
   int j0, m0;
   dir_angles(d, &th, &ph);
@@ -573,14 +636,19 @@ static void render_pixel(const orc_scene *s, const orc_view *v, const orc_tol *t
 int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_t npix,
                const int64_t *pix, double *rgba, double *cand, int32_t *ncand,
                int32_t *flags, orc_counts *counts) {
-  if (!s || !v || !rgba || s->k <= 0 || s->D <= 0 || s->D > 16 || s->l <= 0 || v->N <= 0 ||
-      v->H <= 0 || v->W <= 0 || !s->beta || (!s->sigma && (!s->slot || s->sb <= 0)))
+  if (!s || !v || !rgba || s->k <= 0 || s->D <= 0 || s->D > 16 || s->l <= 0 || v->N < 0 ||
+      (v->N == 0 && s->pos_linear) || v->H <= 0 || v->W <= 0 || !s->beta ||
+      (!s->sigma && (!s->slot || s->sb <= 0)))
     return -1;
   if (counts) memset(counts, 0, sizeof *counts);
   ray_work w = {0};
-  if (work_reserve(&w, v->N)) return -1;
+  int nseg = 3 * (s->k + 1) + 2;
+  if (work_reserve(&w, v->N > nseg ? v->N : nseg)) return -1;
+  double *ts = malloc(sizeof(double) * (size_t)nseg);
   cand_list *cl = malloc(sizeof *cl);
-  if (!cl) {
+  if (!cl || !ts) {
+    free(cl);
+    free(ts);
     work_free(&w);
     return -1;
   }
@@ -589,12 +657,13 @@ int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_
     int64_t id = pix ? pix[q] : q;
     if (id < 0 || id >= total) {
       free(cl);
+      free(ts);
       work_free(&w);
       return -1;
     }
     int x = (int)(id % v->W), y = (int)(id / v->W);
     int32_t f;
-    render_pixel(s, v, tol, x, y, &w, rgba + 4 * q, cl, &f, counts);
+    render_pixel(s, v, tol, x, y, &w, ts, rgba + 4 * q, cl, &f, counts);
     if (flags) flags[q] = f;
     if (counts) {
       counts->ambiguous_pixels += (f & ORC_AMBIG) != 0;
@@ -607,6 +676,7 @@ int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_
     if (ncand) ncand[q] = cl->n;
   }
   free(cl);
+  free(ts);
   work_free(&w);
   return 0;
 }
@@ -614,6 +684,7 @@ int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_
 int orc_trace(const orc_scene *s, const orc_view *v, int32_t x, int32_t y, double *t,
               double *sigma, double *rgb, double *delta) {
   double o[3], d[3], t0, t1;
+  if (v->N <= 0) return -1;
   orc_pixel_ray(v, x, y, o, d);
   if (!orc_interval(s, v, o, d, &t0, &t1)) return 0;
   ray_work w = {0};

@@ -59,7 +59,7 @@ typedef struct {
   double c2w[12];       /* 3x4 camera-to-world, row-major, columns right, down, forward, eye */
   int32_t H, W;
   double near, far;
-  int32_t N;
+  int32_t N;            /* samples per ray; 0 = every voxel the ray crosses (nearest only) */
   double eps;           /* termination threshold on transmittance; 0 = never stop */
 } orc_view;
 
