@@ -135,16 +135,19 @@ fastnerf_status fastnerf_cache_destroy(fastnerf_cache cache);
 
 /* ---------------------------------------------------------------- rendering */
 
-/* Renders one H x W view into out (device, float[H][W][4]). N in [1, 4096],
- * near < far, eps in [0, 1). One persistent launch on `stream`; asynchronous.
- * [Sec. 3.1 Eq. 1, Sec. 3.2 Eq. 5, Sec. 4] */
+/* Renders one H x W view into out (device, float[H][W][4]). N in [1, 4096]
+ * samples per ray, or N = 0 to visit every voxel the ray crosses inside
+ * [near, far] and the box, each with the length of the ray inside it (the
+ * per-voxel integration of Sec. 4; nearest position lookups and k <= 1024,
+ * EINVAL otherwise). near < far, eps in [0, 1). One persistent launch on
+ * `stream`; asynchronous. [Sec. 3.1 Eq. 1, Sec. 3.2 Eq. 5, Sec. 4] */
 fastnerf_status fastnerf_render(fastnerf_cache cache, const float K[9], const float c2w[12],
                                 int32_t H, int32_t W, float near, float far, int32_t N, float eps,
                                 float *out, hipStream_t stream);
 
 /* Renders nviews views of one cache in a single persistent launch. K, c2w,
  * H, W, near, far and out are host arrays of nviews entries (out[i] is a
- * device buffer of H[i]*W[i]*4 floats). */
+ * device buffer of H[i]*W[i]*4 floats). N as for fastnerf_render. */
 fastnerf_status fastnerf_render_batch(fastnerf_cache cache, int32_t nviews, const float *K,
                                       const float *c2w, const int32_t *H, const int32_t *W,
                                       const float *near, const float *far, int32_t N, float eps,
@@ -176,8 +179,9 @@ double fastnerf_model_bytes(double alpha, int64_t k, int64_t l, int32_t D, doubl
 fastnerf_status fastnerf_server_create(const fastnerf_cache *scenes, int32_t nscenes,
                                        uint64_t arena_bytes, int32_t max_inflight,
                                        fastnerf_server *out);
-/* Non-blocking. EBUSY when the queue is full, ENOMEM when the request can
- * never fit the arena, ESHUTDOWN after destroy began. */
+/* Non-blocking. N in [1, 4096] (no voxel traversal in serving steps).
+ * EBUSY when the queue is full, ENOMEM when the request can never fit the
+ * arena, ESHUTDOWN after destroy began. */
 fastnerf_status fastnerf_serve_submit(fastnerf_server server, int32_t scene, const float K[9],
                                       const float c2w[12], int32_t H, int32_t W, float near,
                                       float far, int32_t N, float eps, uint64_t *ticket);

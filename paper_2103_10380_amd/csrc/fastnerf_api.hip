@@ -131,13 +131,13 @@ struct LaunchPlan {
   int block, grid;
 };
 
-LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles) {
+LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox) {
   static std::mutex mu;
   static std::map<std::pair<int, int>, int> plans;  // (device, variant) -> resident blocks
   int dev = 0;
   (void)hipGetDevice(&dev);
   const bool lin = c->desc.pos_interp == FASTNERF_LINEAR;
-  const int variant = (int)c->desc.storage * 64 + (lin ? 32 : 0) +
+  const int variant = (int)c->desc.storage * 64 + (lin ? 32 : 0) + (vox ? 16 : 0) +
                       (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
   int blocks;
   {
@@ -149,7 +149,8 @@ LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles) {
       if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
           cus < 1)
         cus = 1;
-      const int per_cu = render_occupancy((int)c->desc.storage, lin, c->desc.D);
+      const int per_cu = vox ? render_vox_occupancy((int)c->desc.storage, c->desc.D)
+                             : render_occupancy((int)c->desc.storage, lin, c->desc.D);
       it = plans.emplace(key, cus * (per_cu < 1 ? 1 : per_cu)).first;
     }
     blocks = it->second;
@@ -239,8 +240,17 @@ DevCache dev_cache(const fastnerf_cache_s *c) {
   return d;
 }
 
+// Voxel traversal (N = 0) needs nearest lookups and a 32-bit record index.
+static fastnerf_status check_voxel_mode(const fastnerf_cache_s *c, int N) {
+  if (N != 0) return FASTNERF_OK;
+  if (c->desc.pos_interp != FASTNERF_NEAREST)
+    return fail(FASTNERF_EINVAL, "N = 0 (voxel traversal) needs nearest position lookups");
+  if (c->desc.k > 1024) return fail(FASTNERF_EINVAL, "N = 0 (voxel traversal) needs k <= 1024");
+  return FASTNERF_OK;
+}
+
 fastnerf_status check_render_params(int N, float eps) {
-  if (N < 1 || N > 4096) return fail(FASTNERF_EINVAL, "N = %d outside [1, 4096]", N);
+  if (N < 0 || N > 4096) return fail(FASTNERF_EINVAL, "N = %d outside [0, 4096]", N);
   if (!(eps >= 0.0f && eps < 1.0f)) return fail(FASTNERF_EINVAL, "eps outside [0, 1)");
   return FASTNERF_OK;
 }
@@ -250,12 +260,13 @@ float eps_limit(float eps) { return eps > 0.0f ? (float)log(1.0 / (double)eps) :
 fastnerf_status enqueue_render(fastnerf_cache_s *c, const RenderArgs &a0, int total_tiles,
                                StreamState *st, hipStream_t s) {
   RenderArgs a = a0;
-  const LaunchPlan p = launch_plan(c, total_tiles);
+  const LaunchPlan p = launch_plan(c, total_tiles, a.vox != 0);
   a.counter = st->counter;
   a.nwaves = (unsigned)p.grid * (p.block / kWave);
   a.total_tiles = total_tiles;
-  hipError_t e = launch_render((int)c->desc.storage, c->desc.pos_interp == FASTNERF_LINEAR, a,
-                               p.grid, s);
+  hipError_t e = a.vox ? launch_render_vox((int)c->desc.storage, a, p.grid, s)
+                       : launch_render((int)c->desc.storage,
+                                       c->desc.pos_interp == FASTNERF_LINEAR, a, p.grid, s);
   if (e != hipSuccess) return hip_fail(e, "render launch");
   HIP_TRY(hipEventRecord(c->last_use, s));
   return FASTNERF_OK;
@@ -554,6 +565,7 @@ extern "C" fastnerf_status fastnerf_render(fastnerf_cache c, const float K[9],
   if (!c->finalized) return fail(FASTNERF_EINVAL, "cache not finalized");
   fastnerf_status st = check_view(K, c2w, H, W, near_, far_, out);
   if (st == FASTNERF_OK) st = check_render_params(N, eps);
+  if (st == FASTNERF_OK) st = check_voxel_mode(c, N);
   if (st != FASTNERF_OK) return st;
   StreamState *ss = nullptr;
   st = stream_state(s, &ss);
@@ -566,6 +578,7 @@ extern "C" fastnerf_status fastnerf_render(fastnerf_cache c, const float K[9],
   a.v0.lim = eps_limit(eps);
   a.views = nullptr;
   a.nviews = 1;
+  a.vox = N == 0;
   const int tiles = ((W + 7) / 8) * ((H + 7) / 8);
   return enqueue_render(c, a, tiles, ss, s);
 }
@@ -582,6 +595,7 @@ extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nview
   if (!K || !c2w || !H || !W || !near_ || !far_ || !out)
     return fail(FASTNERF_EINVAL, "null view array");
   fastnerf_status st = check_render_params(N, eps);
+  if (st == FASTNERF_OK) st = check_voxel_mode(c, N);
   if (st != FASTNERF_OK) return st;
   int64_t total = 0;
   for (int v = 0; v < nviews; ++v) {
@@ -611,6 +625,7 @@ extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nview
   a.c = dev_cache(c);
   a.views = ss->views;
   a.nviews = nviews;
+  a.vox = N == 0;
   return enqueue_render(c, a, (int)total, ss, s);
 }
 

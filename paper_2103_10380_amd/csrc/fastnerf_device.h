@@ -80,6 +80,7 @@ struct RenderArgs {
   unsigned nwaves;
   const DevCache *caches;   // serving: per-scene caches (device), views[i].scene indexes it
   const int *dyn_total;     // serving: {tile count, view count} of the step (device)
+  int vox;                  // 1: voxel traversal (every view has N = 0)
 };
 
 // ------------------------------------------------------------------ storage formats

@@ -12,6 +12,9 @@ constexpr int kQueueCounters = 32 * 32;
 int render_step_occupancy(bool lin, int D);
 hipError_t launch_render_step(bool lin, int D, const RenderArgs &a, int grid, hipStream_t s);
 hipError_t launch_render(int fmt, bool lin, const RenderArgs &a, int grid, hipStream_t s);
+// Voxel traversal (views with N = 0; nearest lookups, k <= 1024).
+int render_vox_occupancy(int fmt, int D);
+hipError_t launch_render_vox(int fmt, const RenderArgs &a, int grid, hipStream_t s);
 hipError_t launch_absmax(const float *sigma, const float *u, int64_t nvox, int D, unsigned *amax,
                          hipStream_t s);
 hipError_t launch_make_scales(const unsigned *amax, int nch, float *scales, hipStream_t s);

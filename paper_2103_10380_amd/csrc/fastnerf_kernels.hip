@@ -271,6 +271,219 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
   reinterpret_cast<float4 *>(V.out)[(size_t)py * W + px] = res;
 }
 
+// ------------------------------------------------------------------ voxel traversal
+
+// Pieces of a ray generated per window of the voxel traversal.
+#ifndef FNR_VWIN
+#define FNR_VWIN 8
+#endif
+constexpr int kVWin = FNR_VWIN;
+constexpr float kVInf = 3.0e38f;
+
+// Distance (from the interval start, in t) to the next crossing of a cell
+// boundary along one axis from cell c, moving by step (+1/-1); cell
+// boundaries sit at grid coordinates i - kTie for i = 1..k-1 (the first and
+// last cells end at the box faces, where the interval ends).
+__device__ __forceinline__ float vox_next(int c, int step, int k, float og, float igd) {
+  if (step == 0) return kVInf;
+  const int b = step > 0 ? c + 1 : c;  // boundary index
+  if (b < 1 || b > k - 1) return kVInf;
+  return ((float)b - kTie - og) * igd;
+}
+
+// Renders the rays of one 8x8 tile by visiting every voxel each ray crosses
+// inside [near, far] and the box (N = 0): each piece between consecutive cell
+// boundaries is one sample with delta = its length (Eq. 1 with the piece
+// lengths; nearest lookups). Pieces are produced kVWin at a time by stepping
+// from boundary to boundary (each crossing computed directly from its index,
+// not accumulated), their bricks tested with independent loads, and the
+// occupied ones gathered and composited in order. The brick distance of the
+// last piece lets the traversal restart past the space it proves empty.
+template <int FMT, int MAXD>
+__device__ __forceinline__ void render_tile_vox(const RenderArgs &a, const DevCache &c,
+                                                const DevView &V, int lt, int lane) {
+  using RW = RecWords<FMT, MAXD>;
+  constexpr int B = Batch<FMT, false>::value;
+  const int W = V.W, H = V.H;
+  const int px = (lt % V.tiles_x) * 8 + (lane & 7);
+  const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
+  if (px >= W || py >= H) return;
+  const int k = c.k;
+  // FP64 ray set-up, as in render_tile; the interval is always clipped to the box
+  const double qx = (double)px + 0.5, qy = (double)py + 0.5;
+  double ddx = fma(V.M[0], qx, fma(V.M[1], qy, V.M[2]));
+  double ddy = fma(V.M[3], qx, fma(V.M[4], qy, V.M[5]));
+  double ddz = fma(V.M[6], qx, fma(V.M[7], qy, V.M[8]));
+  const double rn = 1.0 / sqrt(fma(ddx, ddx, fma(ddy, ddy, ddz * ddz)));
+  ddx *= rn;
+  ddy *= rn;
+  ddz *= rn;
+  double t0 = V.near_, t1 = V.far_;
+  {
+    const double d3[3] = {ddx, ddy, ddz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const double lo = c.bmin[ax], hi = c.bmax[ax];
+      if (d3[ax] == 0.0) {
+        if (V.o[ax] < lo || V.o[ax] > hi) t1 = -1.0;
+      } else {
+        const double ta = (lo - V.o[ax]) / d3[ax], tb = (hi - V.o[ax]) / d3[ax];
+        t0 = fmax(t0, fmin(ta, tb));
+        t1 = fmin(t1, fmax(ta, tb));
+      }
+    }
+  }
+  float tau = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  if (t1 > t0) {
+    float cw[ColourWeights<FMT, MAXD>::n];
+    float s0 = 1.0f;
+    {
+      float beta[MAXD];
+      dir_lookup<MAXD>(c, (float)ddx, (float)ddy, (float)ddz, beta);
+#pragma unroll
+      for (int d = 0; d < MAXD; ++d) {
+        if (FMT == 3) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) cw[3 * d + ch] = beta[d] * c.scales[1 + 3 * d + ch];
+        } else {
+          cw[d] = beta[d];
+        }
+      }
+      if (FMT == 3) s0 = c.scales[0];
+    }
+    const float L = (float)(t1 - t0);
+    const float og[3] = {(float)((fma(t0, ddx, V.o[0]) - c.bmin[0]) * c.inv_h[0]),
+                         (float)((fma(t0, ddy, V.o[1]) - c.bmin[1]) * c.inv_h[1]),
+                         (float)((fma(t0, ddz, V.o[2]) - c.bmin[2]) * c.inv_h[2])};
+    const float gd[3] = {(float)(ddx * c.inv_h[0]), (float)(ddy * c.inv_h[1]),
+                         (float)(ddz * c.inv_h[2])};
+    int step[3];
+    float igd[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      step[ax] = gd[ax] > 0.0f ? 1 : (gd[ax] < 0.0f ? -1 : 0);
+      igd[ax] = step[ax] != 0 ? 1.0f / gd[ax] : 0.0f;
+    }
+    const float gmax = fmaxf(fabsf(gd[0]), fmaxf(fabsf(gd[1]), fabsf(gd[2])));
+    const float bedge = (float)(1 << c.oshift);
+    // traversal state: position s along [0, L], current cell, next crossings
+    float sc = 0.0f;
+    int cell[3];
+    float sn[3];
+    bool restart = true;
+    bool alive = true;
+    while (alive && sc < L) {
+      if (restart) {  // (re)enter the grid at sc
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const float g = fmaf(sc, gd[ax], og[ax]);
+          cell[ax] = min(max((int)floorf(g + kTie), 0), k - 1);
+          sn[ax] = vox_next(cell[ax], step[ax], k, og[ax], igd[ax]);
+          if (sn[ax] <= sc) {  // on (or rounded past) the boundary: the next cell
+            cell[ax] = min(max(cell[ax] + step[ax], 0), k - 1);
+            sn[ax] = vox_next(cell[ax], step[ax], k, og[ax], igd[ax]);
+          }
+        }
+        restart = false;
+      }
+      // the window's pieces: record index, bitgrid bit, length
+      uint32_t rec[kVWin], bit[kVWin];
+      float len[kVWin];
+      uint32_t valid = 0u;
+#pragma unroll
+      for (int j = 0; j < kVWin; ++j) {
+        const float se = fminf(fminf(sn[0], sn[1]), fminf(sn[2], L));
+        const bool v = sc < L;
+        len[j] = v ? se - sc : 0.0f;
+        valid |= (uint32_t)v << j;
+        const int x = cell[0], y = cell[1], z = cell[2];
+        const uint32_t lb = ((uint32_t)(z >> 3) * (uint32_t)c.nbl + (uint32_t)(y >> 3)) *
+                                (uint32_t)c.nbl + (uint32_t)(x >> 3);
+        rec[j] = (lb << 9) | ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
+        bit[j] = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo + (uint32_t)(y >> c.oshift)) *
+                     (uint32_t)c.nbo + (uint32_t)(x >> c.oshift);
+        // advance every axis whose boundary is crossed at se
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          if (v && sn[ax] <= se) {
+            cell[ax] = min(max(cell[ax] + step[ax], 0), k - 1);
+            sn[ax] = vox_next(cell[ax], step[ax], k, og[ax], igd[ax]);
+          }
+        }
+        sc = v ? se : sc;
+      }
+      uint32_t word[kVWin];
+#pragma unroll
+      for (int j = 0; j < kVWin; ++j) word[j] = __ldg(c.occ + (bit[j] >> 5));
+      const uint32_t dlast = __ldg(c.dist + bit[kVWin - 1]);
+      uint32_t mask = 0u;
+#pragma unroll
+      for (int j = 0; j < kVWin; ++j) mask |= ((word[j] >> (bit[j] & 31u)) & 1u) << j;
+      mask &= valid;
+      while (mask != 0u && alive) {
+        uint32_t ri[B];
+        float li[B];
+        bool have[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          have[b] = mask != 0u;
+          ri[b] = ri[0];
+          li[b] = 0.0f;
+          if (have[b]) {
+            const int j = __builtin_ctz(mask);
+            mask &= mask - 1u;
+            // select the j-th piece (j is lane-varying: a short select chain)
+            uint32_t r = rec[0];
+            float l = len[0];
+#pragma unroll
+            for (int q = 1; q < kVWin; ++q) {
+              r = q == j ? rec[q] : r;
+              l = q == j ? len[q] : l;
+            }
+            ri[b] = r;
+            li[b] = l;
+          }
+        }
+        uint32_t w[B][RW::nwords];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+          load_record<FMT, MAXD>(c, (uint64_t)ri[b] << c.rec_shift, w[b]);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+#pragma clang fp contract(off)
+          const bool use = have[b] && alive;
+          const float sg = rec_sigma<FMT>(w[b], s0);
+          float r, g, bl;
+          rec_colour<FMT, MAXD>(w[b], cw, r, g, bl);
+          const float sd = use ? sg * li[b] : 0.0f;
+          const float wgt = expf(-tau) * -expm1f(-sd);
+          cr = fmaf(wgt, r, cr);
+          cg = fmaf(wgt, g, cg);
+          cb = fmaf(wgt, bl, cb);
+          tau = tau + sd;
+          alive = alive && !(tau > V.lim);
+        }
+      }
+      // every point within (d - 1) brick edges (max norm) of the window's end
+      // lies in an unset brick: restart past it
+      if (alive && dlast >= 2u && sc < L) {
+        const float run = (((float)(dlast - 1u) * bedge - 0.5f)) / gmax;
+        if (run > 0.0f) {
+          sc = fminf(sc + run, L);
+          restart = true;
+        }
+      }
+    }
+  }
+  const float T = expf(-tau);
+  float4 res;
+  res.x = fmaf(T, c.bg[0], cr);
+  res.y = fmaf(T, c.bg[1], cg);
+  res.z = fmaf(T, c.bg[2], cb);
+  res.w = -expm1f(-tau);
+  reinterpret_cast<float4 *>(V.out)[(size_t)py * W + px] = res;
+}
+
 // Independent tile queues: all waves fetching from one counter serialise on
 // that address, so tiles are dealt round-robin to kQueues counters 128 bytes
 // apart; the waves of block b take tiles q, q + R, q + 2R, ... with
@@ -342,6 +555,24 @@ __global__ void __launch_bounds__(kBlock, FNR_MIN_WAVES) k_render(RenderArgs a) 
       render_tile<FMT, MAXD, LIN>(a, a.c, V, tile - V.tile_begin + V.tile_offset, lane);
     } else {
       render_tile<FMT, MAXD, LIN>(a, a.c, a.v0, tile, lane);
+    }
+  }
+  queue_retire(Q, lane);
+}
+
+// Voxel traversal (N = 0) over single views or a batch of views.
+template <int FMT, int MAXD>
+__global__ void __launch_bounds__(kBlock) k_render_vox(RenderArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const Queue Q = make_queue(a, a.total_tiles);
+  for (;;) {
+    const int tile = queue_fetch(Q, lane);
+    if (tile < 0) break;
+    if (a.views) {
+      const DevView V = a.views[view_of_tile(a, tile, a.nviews)];
+      render_tile_vox<FMT, MAXD>(a, a.c, V, tile - V.tile_begin + V.tile_offset, lane);
+    } else {
+      render_tile_vox<FMT, MAXD>(a, a.c, a.v0, tile, lane);
     }
   }
   queue_retire(Q, lane);
@@ -719,6 +950,52 @@ int render_occupancy(int fmt, bool lin, int D) {
 
 hipError_t launch_render(int fmt, bool lin, const RenderArgs &a, int grid, hipStream_t s) {
   return dispatch(fmt, lin, a.c.D, &a, grid, s, nullptr);
+}
+
+namespace {
+
+template <int FMT, int MAXD>
+hipError_t vox_t(const RenderArgs *a, int grid, hipStream_t s, int *occ) {
+  if (a) {
+    hipLaunchKernelGGL((k_render_vox<FMT, MAXD>), dim3(grid), dim3(kBlock), 0, s, *a);
+    return hipGetLastError();
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_vox<FMT, MAXD>, kBlock, 0) !=
+      hipSuccess)
+    nb = 1;
+  *occ = nb < 1 ? 1 : nb;
+  return hipSuccess;
+}
+
+template <int FMT>
+hipError_t vox_d(int D, const RenderArgs *a, int grid, hipStream_t s, int *occ) {
+  switch (maxd_class(D)) {
+    case 4: return vox_t<FMT, 4>(a, grid, s, occ);
+    case 8: return vox_t<FMT, 8>(a, grid, s, occ);
+    default: return vox_t<FMT, 16>(a, grid, s, occ);
+  }
+}
+
+hipError_t vox_dispatch(int fmt, int D, const RenderArgs *a, int grid, hipStream_t s, int *occ) {
+  switch (fmt) {
+    case 0: return vox_d<0>(D, a, grid, s, occ);
+    case 1: return vox_d<1>(D, a, grid, s, occ);
+    case 2: return vox_d<2>(D, a, grid, s, occ);
+    default: return vox_d<3>(D, a, grid, s, occ);
+  }
+}
+
+}  // namespace
+
+int render_vox_occupancy(int fmt, int D) {
+  int occ = 1;
+  (void)vox_dispatch(fmt, D, nullptr, 0, nullptr, &occ);
+  return occ;
+}
+
+hipError_t launch_render_vox(int fmt, const RenderArgs &a, int grid, hipStream_t s) {
+  return vox_dispatch(fmt, a.c.D, &a, grid, s, nullptr);
 }
 
 hipError_t launch_absmax(const float *sigma, const float *u, int64_t nvox, int D, unsigned *amax,

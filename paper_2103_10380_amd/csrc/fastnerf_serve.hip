@@ -220,6 +220,8 @@ extern "C" fastnerf_status fastnerf_serve_submit(fastnerf_server s, int32_t scen
   static const float dummy = 0.0f;
   fastnerf_status st = check_view(K, c2w, H, W, near_, far_, &dummy);
   if (st == FASTNERF_OK) st = check_render_params(N, eps);
+  if (st == FASTNERF_OK && N == 0)
+    st = fail(FASTNERF_EINVAL, "serving renders N >= 1 samples per ray");
   if (st != FASTNERF_OK) return st;
   std::unique_ptr<fs::Request> r(new fs::Request());
   r->scene = scene;

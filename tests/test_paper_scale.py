@@ -1,8 +1,7 @@
 """The paper-scale workload at full size (k=768, D=8, l=384, 800x800, N=192 in
-the box, 8^3 bricks), rendered exactly as bench.py times it (one
-fastnerf_render launch per view), checked on sampled pixels against the oracle
-(nearest-voxel decisions in FP32, reading R13b) computed one pixel at a time
-on a brick-sparse copy of the same scene."""
+the box, 8^3 bricks), checked on sampled pixels against the oracle computed
+one pixel at a time on a brick-sparse copy of the same scene; also the voxel
+traversal (N = 0) of the same scene."""
 import numpy as np
 import pytest
 
@@ -78,3 +77,23 @@ def test_reduced_precision_sampled(scene, storage):
         assert err32.max() <= G.F16_COST_TOL
     else:
         assert G.psnr(gpu, ref32["rgba"]) >= G.FP8_MIN_PSNR
+
+
+def test_voxel_traversal_sampled_parity(scene):
+    """N = 0: every voxel a ray crosses, on the k=768 cache (FP32), sampled
+    pixels against the oracle's plane-crossing traversal."""
+    import torch
+    import paper_2103_10380_amd as fn
+    spec, beta, caches, sparse = scene
+    v = synth.paper_orbit(40)[9]
+    pix = _sample(v, 600, 9)
+    out = fn.render(caches["f32"], v.K, v.c2w, v.H, v.W, v.near, v.far, 0, EPS)
+    torch.cuda.synchronize()
+    gpu = out.reshape(-1, 4)[torch.as_tensor(pix, device="cuda")].cpu().numpy().astype(np.float64)
+    res = G.oracle_render(oracle.Scene(beta, k=spec.k, sparse=sparse, in_box=True), v, 0, EPS,
+                          pix=pix)
+    err, failing, _ = G.compare(gpu, res, G.F32_COST_TOL)
+    print(f"voxel traversal: max err {err:.2e} over {len(pix)} pixels, "
+          f"{res['counts']['occ_samples']} pieces in occupied bricks")
+    assert failing == 0, err
+    assert res["counts"]["hit"] > 200
