@@ -274,6 +274,53 @@ def batched_uneven(fn, reps=10):
             "mrays_per_s": round(rays / (float(np.mean(ms)) / 1e3) / 1e6, 1)}
 
 
+def voxel_sweep(fn, main=None, ks=(256, 384, 512, 768), nviews=8, reps=3, pix=200):
+    """The per-voxel integration (N = 0: every voxel a ray crosses) against N=192
+    samples in the box, on the paper-scale generator at several k (seed 1,
+    FP32 caches), the first nviews views of the 800x800 orbit in one launch
+    each; sampled pixels of one view against the oracle's traversal. main =
+    (k, FP32 cache, brick-sparse copy or None, beta) of the scene already
+    built, reused at its k."""
+    import oracle
+    import synth
+    import torch
+    out = {}
+    views = synth.paper_orbit(40)[:nviews]
+    rays = sum(v.H * v.W for v in views)
+    for k in ks:
+        spec = synth.paper_scene_spec(k=k)
+        if main is not None and main[0] == k and main[1] is not None:
+            _, cache, sparse, beta = main
+            own = False
+        else:
+            p_, beta, cs, sparse, _ = build_caches(spec, ["f32"], True, "cuda")
+            cache, own = cs["f32"], True
+        row = {}
+        for name, N in (("voxels", 0), ("n192", 192)):
+            outs = [torch.empty((v.H, v.W, 4), dtype=torch.float32, device="cuda") for v in views]
+            ms = time_launches(lambda: fn.render_batch(cache, views, N, 1e-4, outs=outs), reps, 1)
+            row[name] = {"ms_per_view": round(float(np.mean(ms)) / nviews, 4),
+                         "mrays_per_s": round(rays / (float(np.mean(ms)) / 1e3) / 1e6, 1)}
+            if N == 0 and sparse is not None:
+                v = views[1]
+                rng = np.random.default_rng(k)
+                px = np.sort(rng.choice(v.H * v.W, pix, replace=False))
+                g = outs[1].reshape(-1, 4)[torch.as_tensor(px, device="cuda")].cpu().numpy()
+                sc = oracle.Scene(beta, k=k, sparse=sparse, in_box=True, occ_brick=8)
+                r = oracle.render(sc, v.K, v.c2w, v.H, v.W, v.near, v.far, 0, 1e-4, pix=px,
+                                  tol=oracle.DEFAULT_TOL)
+                err, ok = oracle.matches(g.astype(np.float64), r, 1e-4)
+                row["voxels"]["parity_max_abs_err"] = float(err.max())
+                row["voxels"]["parity_failing"] = int((~ok).sum())
+                row["voxels"]["occupied_pieces_per_hit_ray"] = round(
+                    r["counts"]["occ_samples"] / max(1, r["counts"]["hit"]), 2)
+        out[str(k)] = row
+        log(f"voxel traversal k={k}: {row}")
+        if own:
+            cache.destroy()
+    return out
+
+
 SERVE_RES = [(400, 400), (800, 800), (1280, 720), (1920, 1080)]
 
 
@@ -631,6 +678,7 @@ def main():
             r["scenes"] = "paper-scale k=768 FP16 and FP8 caches of this run"
             line["serving_sample"] = r
             log(f"serving sample: p50 {r['latency_ms_p50']} ms p99 {r['latency_ms_p99']} ms")
+        line["voxel_traversal"] = voxel_sweep(fn, (spec.k, caches.get("f32"), sparse, beta))
         for c in caches.values():
             c.destroy()
         caches = {}
