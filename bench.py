@@ -46,6 +46,12 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def storage_of(name):
+    """Cache format and brick-sparsity of a storage name: "fp8" is a dense FP8
+    cache, "fp8s" the brick-sparse one."""
+    return (name[:-1], True) if name.endswith("s") else (name, False)
+
+
 def build_caches(spec, storages, want_sparse, device):
     """Generates the scene slab by slab on the GPU and uploads it to one cache
     per storage format; optionally keeps a brick-sparse host copy."""
@@ -55,17 +61,21 @@ def build_caches(spec, storages, want_sparse, device):
     beta = synth.beta_table(p)
     caches = {}
     for st in storages:
-        desc = fn.make_desc(spec.k, spec.D, spec.l, storage=st, brick=8,
-                            sample_mode=fn.IN_BOX)
+        base, is_sparse = storage_of(st)
+        desc = fn.make_desc(spec.k, spec.D, spec.l, storage=base, brick=8,
+                            sample_mode=fn.IN_BOX, sparse=is_sparse)
         caches[st] = fn.Cache.create_empty(desc, beta)
     k, sb = spec.k, 8
-    if "fp8" in caches:  # per-channel scales need the whole cache first
+    # FP8 scales and the stored bricks of sparse caches need the whole cache first
+    scanned = [st for st in storages if storage_of(st)[0] == "fp8" or storage_of(st)[1]]
+    if scanned:
         for z0 in range(0, k, sb):
             if z0 % (16 * sb) == 0:
                 log(f"scan slab z0={z0}/{k}")
             sig = synth.density(p, z0, sb, device)
             u = synth.radiance(p, z0, sb, device)
-            caches["fp8"].scan_slab(z0, sig, u)
+            for st in scanned:
+                caches[st].scan_slab(z0, sig, u)
     nb = k // sb
     slot = np.full(nb ** 3, -1, np.int32) if want_sparse else None
     ss, su, n, occ_vox = [], [], 0, 0
@@ -473,8 +483,9 @@ def main():
     ap.add_argument("--views", type=int, default=40)
     ap.add_argument("--k", type=int, default=768)
     ap.add_argument("--no-variants", action="store_true", help="FP32 cache only")
-    ap.add_argument("--storages", default="f32,f16,fp8",
-                    help="comma-separated cache formats to time (f32 is always included)")
+    ap.add_argument("--storages", default="f32,f16,fp8,f32s,fp8s",
+                    help="comma-separated cache formats to time (f32 is always included; "
+                         "a trailing s selects the brick-sparse cache of that format)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle pixels per view")
@@ -555,7 +566,7 @@ def main():
                     time_single(fn, caches[st], views, N, eps, args.steps, args.warmup))
         rays = args.steps * sum(v.H * v.W for v in views)
         results[st] = dict(wall=wall, step_ms=step_ms, frame_ms=frame_ms,
-                           mrays=rays / wall / 1e6)
+                           mrays=rays / wall / 1e6, resident=caches[st].resident_bytes)
         if st == "f32":
             outs_f32 = outs
         else:
@@ -667,7 +678,9 @@ def main():
                         round(float(np.percentile(r["frame_ms"], 50)), 4),
                         "single_view_frame_ms_p99": None if args.no_single else
                         round(float(np.percentile(r["frame_ms"], 99)), 4),
-                        "speedup_vs_f32": round(r["mrays"] / r32["mrays"], 3)}
+                        "speedup_vs_f32": round(r["mrays"] / r32["mrays"], 3),
+                        "resident_gib": round(r["resident"] / 2**30, 3),
+                        "brick_sparse": storage_of(st)[1]}
         if not args.no_cpu and st != "f32":
             variants[st].update({k2: round(v2, 6) for k2, v2 in psnr_in[st].items()})
     line["variants"] = variants

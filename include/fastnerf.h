@@ -82,6 +82,11 @@ typedef struct {
                                 k / brick <= 1024); 0 = no empty-space skipping */
   fastnerf_sample_mode sample_mode;
   float background[3];
+  int32_t sparse;            /* 1: store only the 8^3 bricks that hold a voxel with sigma > 0
+                                (the occupied bricks of the bitgrid); the others read as
+                                zero. Needs nearest lookups, brick = 8 and k % 8 == 0.
+                                0: every voxel is stored. [Sec. 1, supplementary "Meshing &
+                                Rendering": the caches are stored sparsely] */
 } fastnerf_cache_desc;
 
 /* ---------------------------------------------------------------- caches */
@@ -97,10 +102,11 @@ fastnerf_status fastnerf_cache_create(const fastnerf_cache_desc *desc, const flo
                                       fastnerf_cache *out);
 
 /* Slab-wise construction for caches larger than host memory or built on the
- * device: create_empty, then (FP8 only) scan_slab for every slab so that the
- * per-channel scales are known, then upload_slab for every slab, then
- * finalize. A slab is nz consecutive z layers starting at z0, laid out like
- * the full arrays. */
+ * device: create_empty, then (FP8 or sparse caches) scan_slab for every slab
+ * so that the per-channel scales and the stored bricks are known, then
+ * upload_slab for every slab with the same data, then finalize, all on one
+ * stream (or ordered by the caller). A slab is nz consecutive z layers
+ * starting at z0, laid out like the full arrays. */
 fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc *desc, const float *beta,
                                             hipStream_t stream, fastnerf_cache *out);
 fastnerf_status fastnerf_cache_scan_slab(fastnerf_cache cache, int32_t z0, int32_t nz,

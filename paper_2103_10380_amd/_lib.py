@@ -36,7 +36,8 @@ class Desc(ctypes.Structure):
                 ("bbox_min", ctypes.c_float * 3), ("bbox_max", ctypes.c_float * 3),
                 ("storage", ctypes.c_int32), ("pos_interp", ctypes.c_int32),
                 ("dir_interp", ctypes.c_int32), ("brick", ctypes.c_int32),
-                ("sample_mode", ctypes.c_int32), ("background", ctypes.c_float * 3)]
+                ("sample_mode", ctypes.c_int32), ("background", ctypes.c_float * 3),
+                ("sparse", ctypes.c_int32)]
 
 
 # every symbol the header declares: (name, restype, argtypes)
@@ -123,7 +124,7 @@ def _ptr(x):
 
 
 def make_desc(k, D, l, *, storage="f32", pos_interp=NEAREST, dir_interp=LINEAR, brick=8,
-              sample_mode=NEAR_FAR, bbox=(-1.0, 1.0), background=(1.0, 1.0, 1.0)):
+              sample_mode=NEAR_FAR, bbox=(-1.0, 1.0), background=(1.0, 1.0, 1.0), sparse=False):
     d = Desc()
     d.k, d.D, d.l = k, D, l
     lo, hi = bbox
@@ -132,6 +133,7 @@ def make_desc(k, D, l, *, storage="f32", pos_interp=NEAREST, dir_interp=LINEAR, 
     d.storage = DTYPES[storage] if isinstance(storage, str) else int(storage)
     d.pos_interp, d.dir_interp, d.brick, d.sample_mode = pos_interp, dir_interp, brick, sample_mode
     d.background[:] = list(background)
+    d.sparse = 1 if sparse else 0
     return d
 
 

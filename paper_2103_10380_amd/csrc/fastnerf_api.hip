@@ -137,8 +137,9 @@ LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   const bool lin = c->desc.pos_interp == FASTNERF_LINEAR;
+  const bool sparse = c->desc.sparse && !vox;
   const int variant = (int)c->desc.storage * 64 + (lin ? 32 : 0) + (vox ? 16 : 0) +
-                      (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
+                      (sparse ? 8 : 0) + (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
   int blocks;
   {
     std::lock_guard<std::mutex> g(mu);
@@ -150,7 +151,7 @@ LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox) {
           cus < 1)
         cus = 1;
       const int per_cu = vox ? render_vox_occupancy((int)c->desc.storage, c->desc.D)
-                             : render_occupancy((int)c->desc.storage, lin, c->desc.D);
+                             : render_occupancy((int)c->desc.storage, lin, c->desc.D, sparse);
       it = plans.emplace(key, cus * (per_cu < 1 ? 1 : per_cu)).first;
     }
     blocks = it->second;
@@ -216,6 +217,8 @@ DevCache dev_cache(const fastnerf_cache_s *c) {
   d.occ = c->occ;
   d.dist = c->dist;
   d.scales = c->scales;
+  d.slot = ds.sparse ? c->slot : nullptr;
+  d.rank = ds.sparse ? c->rank : nullptr;
   d.k = ds.k;
   d.D = ds.D;
   d.l = ds.l;
@@ -295,6 +298,10 @@ static fastnerf_status validate_desc(const fastnerf_cache_desc *d) {
     if (!isfinite(d->bbox_min[a]) || !isfinite(d->bbox_max[a]) ||
         !(d->bbox_min[a] < d->bbox_max[a]) || !isfinite(d->background[a]))
       return fail(FASTNERF_EINVAL, "bad bounding box or background");
+  if ((unsigned)d->sparse > 1u) return fail(FASTNERF_EINVAL, "sparse must be 0 or 1");
+  if (d->sparse && (d->pos_interp != FASTNERF_NEAREST || d->brick != 8 || d->k % 8))
+    return fail(FASTNERF_EINVAL, "a brick-sparse cache needs nearest lookups, brick = 8 and "
+                                 "k %% 8 == 0");
   return FASTNERF_OK;
 }
 
@@ -325,22 +332,30 @@ extern "C" fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc
     c->oshift = 0;
     c->nbo = 0;
   }
-  const uint64_t nrec = (uint64_t)c->nbl * c->nbl * c->nbl * 512ull;
-  const uint64_t rec_bytes = nrec * (uint64_t)stride;
+  const uint64_t nlb = (uint64_t)c->nbl * c->nbl * c->nbl;
+  // a brick-sparse cache allocates its records once the stored bricks are known
+  const uint64_t rec_bytes = desc->sparse ? 0 : nlb * 512ull * (uint64_t)stride;
   const int dp = (desc->D + 3) / 4 * 4;  // direction-cache row, padded to 16 bytes
   const uint64_t beta_bytes = (uint64_t)desc->l * desc->l * dp * sizeof(float);
   const uint64_t nbits = (uint64_t)c->nbo * c->nbo * c->nbo;
   const uint64_t occ_bytes = ((nbits + 31) / 32 + 1) * 4;
   const uint64_t dist_bytes = nbits > 0 ? nbits : 1;
   const int nch = 1 + 3 * desc->D;
-  hipError_t e = hipMalloc(&c->rec, rec_bytes);
+  const uint64_t nwords = occ_bytes / 4;
+  const uint64_t sparse_bytes = desc->sparse ? nlb * 4 + nwords * 4 : 0;  // slot, rank
+  hipError_t e = hipSuccess;
+  if (rec_bytes) e = hipMalloc(&c->rec, rec_bytes);
+  if (e == hipSuccess && desc->sparse) e = hipMalloc(&c->bflag, nlb * 4);
+  if (e == hipSuccess && desc->sparse) e = hipMalloc(&c->slot, nlb * 4);
+  if (e == hipSuccess && desc->sparse) e = hipMalloc(&c->rank, nwords * 4);
+  if (e == hipSuccess && desc->sparse) e = hipMemsetAsync(c->bflag, 0, nlb * 4, stream);
   if (e == hipSuccess) e = hipMalloc(&c->beta, beta_bytes);
   if (e == hipSuccess) e = hipMalloc(&c->occ, occ_bytes);
   if (e == hipSuccess) e = hipMalloc(&c->dist, dist_bytes);
   if (e == hipSuccess) e = hipMalloc(&c->scales, sizeof(float) * kMaxCh);
   if (e == hipSuccess) e = hipMalloc(&c->amax, sizeof(unsigned) * nch);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->last_use, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMemsetAsync(c->rec, 0, rec_bytes, stream);
+  if (e == hipSuccess && rec_bytes) e = hipMemsetAsync(c->rec, 0, rec_bytes, stream);
   // without a bitgrid the kernels read one all-ones word and one zero distance
   if (e == hipSuccess) e = hipMemsetAsync(c->occ, desc->brick > 0 ? 0 : 0xFF, occ_bytes, stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->dist, 0, dist_bytes, stream);
@@ -362,7 +377,8 @@ extern "C" fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc
     fastnerf_cache_destroy(c);
     return r;
   }
-  c->resident = rec_bytes + beta_bytes + occ_bytes + dist_bytes + sizeof(float) * kMaxCh;
+  c->resident =
+      rec_bytes + sparse_bytes + beta_bytes + occ_bytes + dist_bytes + sizeof(float) * kMaxCh;
   c->occ_bytes = occ_bytes;
   (void)hipGetDevice(&c->device);
   *out = c;
@@ -416,14 +432,60 @@ extern "C" fastnerf_status fastnerf_cache_scan_slab(fastnerf_cache c, int32_t z0
                                                     hipStream_t s) {
   fastnerf_status st = check_slab(c, z0, nz, sigma, u);
   if (st != FASTNERF_OK) return st;
-  if (c->desc.storage != FASTNERF_FP8_E4M3) return FASTNERF_OK;
-  if (c->scales_ready) return fail(FASTNERF_EINVAL, "scan after the first upload");
+  const bool fp8 = c->desc.storage == FASTNERF_FP8_E4M3, sparse = c->desc.sparse != 0;
+  if (!fp8 && !sparse) return FASTNERF_OK;
+  if ((fp8 && c->scales_ready) || (sparse && c->sparse_ready))
+    return fail(FASTNERF_EINVAL, "scan after the first upload");
+  if (sparse) c->scanned = true;
   return for_device_slab(c, z0, nz, sigma, u, s,
-                         [&](const float *ds, const float *du, int, int m) -> fastnerf_status {
-                           hipError_t e = launch_absmax(ds, du, (int64_t)m * c->desc.k * c->desc.k,
-                                                        c->desc.D, c->amax, s);
-                           return e == hipSuccess ? FASTNERF_OK : hip_fail(e, "absmax");
+                         [&](const float *ds, const float *du, int zz, int m) -> fastnerf_status {
+                           hipError_t e = hipSuccess;
+                           if (fp8)
+                             e = launch_absmax(ds, du, (int64_t)m * c->desc.k * c->desc.k,
+                                               c->desc.D, c->amax, s);
+                           if (e == hipSuccess && sparse)
+                             e = launch_brick_flags(ds, zz, m, c->desc.k, c->nbl, c->bflag, s);
+                           return e == hipSuccess ? FASTNERF_OK : hip_fail(e, "slab scan");
                          });
+}
+
+// Brick-sparse caches, at the first upload: from the brick flags of the scan,
+// the bitgrid (bit = brick stored), the set bits before each bitgrid word, the
+// stored slot of every brick (1 + its rank; 0 = the all-zero brick) and the
+// records of the stored bricks, zeroed.
+static fastnerf_status build_sparse_layout(fastnerf_cache_s *c, hipStream_t s) {
+  if (!c->scanned) return fail(FASTNERF_EINVAL, "a brick-sparse cache needs scan_slab first");
+  const uint64_t nlb = (uint64_t)c->nbl * c->nbl * c->nbl;
+  const uint64_t nwords = c->occ_bytes / 4;
+  std::vector<uint32_t> flags(nlb), words(nwords, 0u), rank(nwords, 0u);
+  std::vector<int32_t> slot(nlb, 0);
+  HIP_TRY(hipMemcpyAsync(flags.data(), c->bflag, nlb * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  uint64_t n = 0;
+  for (uint64_t b = 0; b < nlb; ++b) {
+    if ((b & 31) == 0) rank[b >> 5] = (uint32_t)n;
+    if (flags[b]) {
+      words[b >> 5] |= 1u << (b & 31);
+      slot[b] = (int32_t)(++n);
+    }
+  }
+  for (uint64_t w = (nlb + 31) / 32; w < nwords; ++w) rank[w] = (uint32_t)n;
+  const uint64_t rec_bytes = (n + 1) * 512ull * (uint64_t)c->stride;
+  hipError_t e = hipMalloc(&c->rec, rec_bytes);
+  if (e == hipSuccess) e = hipMemsetAsync(c->rec, 0, rec_bytes, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->occ, words.data(), nwords * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->rank, rank.data(), nwords * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->slot, slot.data(), nlb * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "sparse layout");
+  (void)hipFree(c->bflag);
+  c->bflag = nullptr;
+  c->nstored = n;
+  c->resident += rec_bytes;
+  c->sparse_ready = true;
+  return FASTNERF_OK;
 }
 
 extern "C" fastnerf_status fastnerf_cache_upload_slab(fastnerf_cache c, int32_t z0, int32_t nz,
@@ -435,6 +497,10 @@ extern "C" fastnerf_status fastnerf_cache_upload_slab(fastnerf_cache c, int32_t 
     hipError_t e = launch_make_scales(c->amax, 1 + 3 * c->desc.D, c->scales, s);
     if (e != hipSuccess) return hip_fail(e, "scales");
     c->scales_ready = true;
+  }
+  if (c->desc.sparse && !c->sparse_ready) {
+    st = build_sparse_layout(c, s);
+    if (st != FASTNERF_OK) return st;
   }
   const DevCache dc = dev_cache(c);
   return for_device_slab(c, z0, nz, sigma, u, s,
@@ -450,8 +516,10 @@ extern "C" fastnerf_status fastnerf_cache_finalize(fastnerf_cache c, hipStream_t
   if (!c->scales_ready) return fail(FASTNERF_EINVAL, "no slab was uploaded");
   if (c->desc.brick > 0) {
     const DevCache dc = dev_cache(c);
-    hipError_t e = launch_occupancy((int)c->desc.storage, dc,
-                                    c->desc.pos_interp == FASTNERF_LINEAR ? 1 : 0, c->occ, s);
+    hipError_t e = hipSuccess;
+    if (!c->desc.sparse)  // a brick-sparse bitgrid is the stored-brick set
+      e = launch_occupancy((int)c->desc.storage, dc,
+                           c->desc.pos_interp == FASTNERF_LINEAR ? 1 : 0, c->occ, s);
     if (e != hipSuccess) return hip_fail(e, "occupancy");
     const uint64_t nbr = (uint64_t)c->nbo * c->nbo * c->nbo;
     uint8_t *tmp = nullptr;
@@ -551,6 +619,9 @@ extern "C" fastnerf_status fastnerf_cache_destroy(fastnerf_cache c) {
   if (c->dist) (void)hipFree(c->dist);
   if (c->scales) (void)hipFree(c->scales);
   if (c->amax) (void)hipFree(c->amax);
+  if (c->bflag) (void)hipFree(c->bflag);
+  if (c->slot) (void)hipFree(c->slot);
+  if (c->rank) (void)hipFree(c->rank);
   delete c;
   return FASTNERF_OK;
 }

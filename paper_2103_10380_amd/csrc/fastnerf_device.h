@@ -43,6 +43,8 @@ struct DevCache {
   const uint32_t *occ;   // occupancy bits (one all-ones word without a bitgrid)
   const uint8_t *dist;   // per-brick distance to the nearest occupied brick (one 0 without)
   const float *scales;   // kMaxCh per-channel scales (FP8; ones past 1 + 3D and otherwise)
+  const int32_t *slot;   // brick-sparse: record brick of each 8^3 brick (0: all zero); else null
+  const uint32_t *rank;  // brick-sparse: set bitgrid bits before each word
   int k, D, l;
   int bq;                // 16-byte chunks per direction cell (rows of 4 ceil(D/4) floats)
   int nbl;               // layout bricks per axis
@@ -132,8 +134,15 @@ template <int FMT, int MAXD> struct RecWords {
 __device__ inline uint64_t record_offset(const DevCache &c, int x, int y, int z) {
   uint32_t lb = ((uint32_t)(z >> 3) * (uint32_t)c.nbl + (uint32_t)(y >> 3)) * (uint32_t)c.nbl +
                 (uint32_t)(x >> 3);
+  if (c.slot) lb = (uint32_t)c.slot[lb];  // brick-sparse: stored brick (0 reads as zero)
   uint32_t li = ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
   return (((uint64_t)lb << 9) | li) << c.rec_shift;
+}
+
+// Record offset of voxel (x, y, z) in stored brick sb (brick-sparse caches).
+__device__ inline uint64_t record_offset_in(const DevCache &c, uint32_t sb, int x, int y, int z) {
+  const uint32_t li = ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
+  return (((uint64_t)sb << 9) | li) << c.rec_shift;
 }
 
 // Records of a cache rendered with MAXD hold RecWords<FMT, MAXD>::nchunk
@@ -141,6 +150,7 @@ __device__ inline uint64_t record_offset(const DevCache &c, int x, int y, int z)
 // ordinary (L1-allocating) loads: the chunks of one record share a cache line,
 // and with non-temporal loads every 16-byte chunk went to L2 on its own, which
 // halved the speed of the render.
+
 template <int FMT, int MAXD>
 __device__ inline void load_record(const DevCache &c, uint64_t off, uint32_t *w) {
   using RW = RecWords<FMT, MAXD>;

@@ -12,6 +12,13 @@ struct fastnerf_cache_s {
   float *beta = nullptr;       // [l][l][D]
   uint32_t *occ = nullptr;     // occupancy bits
   uint8_t *dist = nullptr;     // per-brick Chebyshev distance to the nearest occupied brick
+  // brick-sparse caches: flags set by scan_slab, then the stored-brick slots
+  // (0 = the all-zero brick) and, per bitgrid word, the set bits before it
+  uint32_t *bflag = nullptr;
+  int32_t *slot = nullptr;
+  uint32_t *rank = nullptr;
+  uint64_t nstored = 0;
+  bool scanned = false, sparse_ready = false;
   float *scales = nullptr;     // 1 + 3D
   unsigned *amax = nullptr;    // FP8 absmax accumulators (float bits)
   int stride = 0, payload = 0, rec_shift = 0, nchunk = 0;

@@ -5,7 +5,7 @@
 namespace fnr {
 
 // Resident blocks per CU of the render kernel (0 if it cannot launch).
-int render_occupancy(int fmt, bool lin, int D);
+int render_occupancy(int fmt, bool lin, int D, bool sparse);
 // Tile queues of a render launch and the spacing of their counters (uints):
 // the counter buffer of a stream holds kQueueCounters uints.
 constexpr int kQueueCounters = 32 * 32;
@@ -22,6 +22,9 @@ hipError_t launch_pack(int fmt, const float *sigma, const float *u, int z0, int 
                        const DevCache &c, hipStream_t s);
 hipError_t launch_occupancy(int fmt, const DevCache &c, int dilate, uint32_t *words,
                             hipStream_t s);
+// Brick-sparse caches: flags of the 8^3 bricks holding a voxel with sigma != 0.
+hipError_t launch_brick_flags(const float *sigma, int z0, int nz, int k, int nbl,
+                              uint32_t *flags, hipStream_t s);
 // Per-brick distance field from the occupancy bits: dist[b] = Chebyshev
 // distance in bricks to the nearest occupied brick, capped at kDistCap. tmp
 // holds nbo^3 bytes of scratch.

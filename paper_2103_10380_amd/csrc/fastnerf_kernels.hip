@@ -44,7 +44,12 @@ template <int FMT, bool LIN> struct Batch {
 };
 
 // Renders the rays of one 8x8 tile (one ray per lane) of view V with cache c.
-template <int FMT, int MAXD, bool LIN>
+// SPARSE: a brick-sparse cache (bitgrid brick = storage brick = 8^3); the
+// stored brick of a flagged sample is its rank among the set bitgrid bits,
+// found from the bitgrid word already loaded by the window scan and the count
+// of set bits before that word (one more independent load), so the gather
+// needs no dependent table lookup.
+template <int FMT, int MAXD, bool LIN, bool SPARSE = false>
 __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache &c,
                                             const DevView &V, int lt, int lane) {
   using RW = RecWords<FMT, MAXD>;
@@ -129,10 +134,11 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
     while (alive) {
       uint32_t mask = 0u;
       int next = i + kWin;
+      uint32_t sslot[SPARSE ? kWin : 1];  // stored brick of each sample (SPARSE)
       {
         // a cache without a bitgrid has one all-ones word and one zero
         // distance, with oshift past every coordinate bit
-        uint32_t word[kWin], bitpos[kWin], dlast = 0u;
+        uint32_t word[kWin], bitpos[kWin], rk[SPARSE ? kWin : 1], dlast = 0u;
         bool in[kWin];
 #pragma unroll
         for (int j = 0; j < kWin; ++j) {
@@ -150,11 +156,18 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
                                (uint32_t)(x >> c.oshift);
           word[j] = __ldg(c.occ + (bit >> 5));
           bitpos[j] = bit & 31u;
+          if (SPARSE) rk[(SPARSE ? j : 0)] = __ldg(c.rank + (bit >> 5));
           if (j == kWin - 1) dlast = __ldg(c.dist + bit);
         }
 #pragma unroll
         for (int j = 0; j < kWin; ++j)
           mask |= (uint32_t)(in[j] && ((word[j] >> bitpos[j]) & 1u)) << j;
+        if (SPARSE) {
+#pragma unroll
+          for (int j = 0; j < kWin; ++j)
+            sslot[(SPARSE ? j : 0)] = 1u + rk[(SPARSE ? j : 0)] +
+                                      (uint32_t)__builtin_popcount(word[j] & ((1u << bitpos[j]) - 1u));
+        }
         if (dlast >= 2u) {
           const float run = fminf(((float)(dlast - 1u) * bedge - 0.5f) * inv_step, (float)N);
           next += (int)run;
@@ -165,13 +178,21 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
         // first sample's voxel, so every load has a valid (cached) address
         int vx[B], vy[B], vz[B];
         float wx[B], wy[B], wz[B];
+        uint32_t sb[B];
         bool have[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
           have[b] = mask != 0u;
+          sb[b] = 0u;
           if (have[b]) {
             const int j = __builtin_ctz(mask);
             mask &= mask - 1u;
+            if (SPARSE) {  // j varies across lanes: a select chain
+              uint32_t v = sslot[0];
+#pragma unroll
+              for (int q = 1; q < kWin; ++q) v = q == j ? sslot[(SPARSE ? q : 0)] : v;
+              sb[b] = v;
+            }
             const float t = ((float)(i + j) + 0.5f) * dt;
             const float gx = fmaf(t, gdx, ogx), gy = fmaf(t, gdy, ogy), gz = fmaf(t, gdz, ogz);
             if (LIN) {
@@ -194,12 +215,15 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
             vy[b] = vy[0];
             vz[b] = vz[0];
             wx[b] = wy[b] = wz[b] = 0.0f;
+            sb[b] = sb[0];
           }
         }
         if (!LIN) {
           uint64_t off[B];
 #pragma unroll
-          for (int b = 0; b < B; ++b) off[b] = record_offset(c, vx[b], vy[b], vz[b]);
+          for (int b = 0; b < B; ++b)
+            off[b] = SPARSE ? record_offset_in(c, sb[b], vx[b], vy[b], vz[b])
+                            : record_offset(c, vx[b], vy[b], vz[b]);
           uint32_t w[B][RW::nwords];
 #pragma unroll
           for (int b = 0; b < B; ++b) load_record<FMT, MAXD>(c, off[b], w[b]);
@@ -420,6 +444,19 @@ __device__ __forceinline__ void render_tile_vox(const RenderArgs &a, const DevCa
 #pragma unroll
       for (int j = 0; j < kVWin; ++j) mask |= ((word[j] >> (bit[j] & 31u)) & 1u) << j;
       mask &= valid;
+      if (c.slot) {
+        // brick-sparse (bitgrid brick = storage brick): the stored brick of a
+        // set bit is 1 + the set bits before it; only set pieces are read
+        uint32_t rk[kVWin];
+#pragma unroll
+        for (int j = 0; j < kVWin; ++j) rk[j] = __ldg(c.rank + (bit[j] >> 5));
+#pragma unroll
+        for (int j = 0; j < kVWin; ++j) {
+          const uint32_t sb =
+              1u + rk[j] + (uint32_t)__builtin_popcount(word[j] & ((1u << (bit[j] & 31u)) - 1u));
+          rec[j] = (sb << 9) | (rec[j] & 511u);
+        }
+      }
       while (mask != 0u && alive) {
         uint32_t ri[B];
         float li[B];
@@ -543,7 +580,7 @@ __device__ __forceinline__ int view_of_tile(const RenderArgs &a, int tile, int n
 #ifndef FNR_MIN_WAVES
 #define FNR_MIN_WAVES 1
 #endif
-template <int FMT, int MAXD, bool LIN>
+template <int FMT, int MAXD, bool LIN, bool SPARSE = false>
 __global__ void __launch_bounds__(kBlock, FNR_MIN_WAVES) k_render(RenderArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const Queue Q = make_queue(a, a.total_tiles);
@@ -552,9 +589,9 @@ __global__ void __launch_bounds__(kBlock, FNR_MIN_WAVES) k_render(RenderArgs a) 
     if (tile < 0) break;
     if (a.views) {
       const DevView V = a.views[view_of_tile(a, tile, a.nviews)];
-      render_tile<FMT, MAXD, LIN>(a, a.c, V, tile - V.tile_begin + V.tile_offset, lane);
+      render_tile<FMT, MAXD, LIN, SPARSE>(a, a.c, V, tile - V.tile_begin + V.tile_offset, lane);
     } else {
-      render_tile<FMT, MAXD, LIN>(a, a.c, a.v0, tile, lane);
+      render_tile<FMT, MAXD, LIN, SPARSE>(a, a.c, a.v0, tile, lane);
     }
   }
   queue_retire(Q, lane);
@@ -664,6 +701,20 @@ __global__ void k_make_scales(const unsigned *amax, int nch, float *scales) {
   }
 }
 
+// Brick-sparse caches: flags[b] = 1 for every 8^3 brick b holding a voxel of
+// the slab with sigma > 0 (a brick without one is empty to the bitgrid too).
+__global__ void k_brick_flags(const float *__restrict__ sigma, int z0, int nz, int k, int nbl,
+                              uint32_t *__restrict__ flags) {
+  const int64_t nvox = (int64_t)nz * k * k;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    if (!(sigma[v] > 0.0f)) continue;
+    const int x = (int)(v % k), y = (int)((v / k) % k), z = z0 + (int)(v / ((int64_t)k * k));
+    flags[((uint32_t)(z >> 3) * (uint32_t)nbl + (uint32_t)(y >> 3)) * (uint32_t)nbl +
+          (uint32_t)(x >> 3)] = 1u;
+  }
+}
+
 template <int FMT>
 __global__ void k_pack(const float *__restrict__ sigma, const float *__restrict__ u, int z0,
                        int nz, DevCache c, float *scales_unused) {
@@ -673,6 +724,9 @@ __global__ void k_pack(const float *__restrict__ sigma, const float *__restrict_
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
        v += (int64_t)gridDim.x * blockDim.x) {
     const int x = (int)(v % k), y = (int)((v / k) % k), z = z0 + (int)(v / ((int64_t)k * k));
+    if (c.slot && c.slot[((uint32_t)(z >> 3) * (uint32_t)c.nbl + (uint32_t)(y >> 3)) *
+                             (uint32_t)c.nbl + (uint32_t)(x >> 3)] == 0)
+      continue;  // brick-sparse: the brick is not stored (it reads as zero)
     uint32_t w[(kMaxCh * 4 + 15) / 16 * 4];
 #pragma unroll
     for (int q = 0; q < (int)(sizeof(w) / 4); ++q) w[q] = 0u;
@@ -840,39 +894,55 @@ namespace {
 
 template <int FMT, int MAXD, bool LIN>
 hipError_t launch_render_t(const RenderArgs &a, int grid, hipStream_t s) {
+  if constexpr (!LIN) {
+    if (a.c.slot) {
+      hipLaunchKernelGGL((k_render<FMT, MAXD, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_render<FMT, MAXD, LIN>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
+// Resident blocks per CU of the render kernel (its brick-sparse variant when
+// sparse is set).
 template <int FMT, int MAXD, bool LIN>
-int occupancy_t() {
+int occupancy_t(bool sparse) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render<FMT, MAXD, LIN>, kBlock, 0) !=
-      hipSuccess)
-    nb = 1;
-  return nb < 1 ? 1 : nb;
+  hipError_t e;
+  if constexpr (!LIN) {
+    e = sparse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                     &nb, k_render<FMT, MAXD, false, true>, kBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render<FMT, MAXD, false>,
+                                                              kBlock, 0);
+  } else {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render<FMT, MAXD, true>, kBlock, 0);
+  }
+  return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 
 template <int FMT, bool LIN>
-hipError_t dispatch_maxd(int D, const RenderArgs *a, int grid, hipStream_t s, int *occ) {
-  if (D <= 4) return a ? launch_render_t<FMT, 4, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 4, LIN>(), hipSuccess);
-  if (D <= 8) return a ? launch_render_t<FMT, 8, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 8, LIN>(), hipSuccess);
-  return a ? launch_render_t<FMT, 16, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 16, LIN>(), hipSuccess);
+hipError_t dispatch_maxd(int D, const RenderArgs *a, int grid, hipStream_t s, bool sparse,
+                         int *occ) {
+  if (D <= 4) return a ? launch_render_t<FMT, 4, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 4, LIN>(sparse), hipSuccess);
+  if (D <= 8) return a ? launch_render_t<FMT, 8, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 8, LIN>(sparse), hipSuccess);
+  return a ? launch_render_t<FMT, 16, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 16, LIN>(sparse), hipSuccess);
 }
 
 template <int FMT>
-hipError_t dispatch_lin(bool lin, int D, const RenderArgs *a, int grid, hipStream_t s, int *occ) {
-  return lin ? dispatch_maxd<FMT, true>(D, a, grid, s, occ)
-             : dispatch_maxd<FMT, false>(D, a, grid, s, occ);
+hipError_t dispatch_lin(bool lin, int D, const RenderArgs *a, int grid, hipStream_t s,
+                        bool sparse, int *occ) {
+  return lin ? dispatch_maxd<FMT, true>(D, a, grid, s, sparse, occ)
+             : dispatch_maxd<FMT, false>(D, a, grid, s, sparse, occ);
 }
 
 hipError_t dispatch(int fmt, bool lin, int D, const RenderArgs *a, int grid, hipStream_t s,
-                    int *occ) {
+                    bool sparse, int *occ) {
   switch (fmt) {
-    case 0: return dispatch_lin<0>(lin, D, a, grid, s, occ);
-    case 1: return dispatch_lin<1>(lin, D, a, grid, s, occ);
-    case 2: return dispatch_lin<2>(lin, D, a, grid, s, occ);
-    default: return dispatch_lin<3>(lin, D, a, grid, s, occ);
+    case 0: return dispatch_lin<0>(lin, D, a, grid, s, sparse, occ);
+    case 1: return dispatch_lin<1>(lin, D, a, grid, s, sparse, occ);
+    case 2: return dispatch_lin<2>(lin, D, a, grid, s, sparse, occ);
+    default: return dispatch_lin<3>(lin, D, a, grid, s, sparse, occ);
   }
 }
 
@@ -942,14 +1012,14 @@ int render_step_occupancy(bool lin, int D) {
   }
 }
 
-int render_occupancy(int fmt, bool lin, int D) {
+int render_occupancy(int fmt, bool lin, int D, bool sparse) {
   int occ = 0;
-  (void)dispatch(fmt, lin, D, nullptr, 0, nullptr, &occ);
+  (void)dispatch(fmt, lin, D, nullptr, 0, nullptr, sparse, &occ);
   return occ;
 }
 
 hipError_t launch_render(int fmt, bool lin, const RenderArgs &a, int grid, hipStream_t s) {
-  return dispatch(fmt, lin, a.c.D, &a, grid, s, nullptr);
+  return dispatch(fmt, lin, a.c.D, &a, grid, s, a.c.slot != nullptr, nullptr);
 }
 
 namespace {
@@ -1036,6 +1106,15 @@ hipError_t launch_occupancy(int fmt, const DevCache &c, int dilate, uint32_t *wo
     case 2: hipLaunchKernelGGL(k_occupancy<2>, dim3(grid), dim3(kBlock), 0, s, c, dilate, words); break;
     default: hipLaunchKernelGGL(k_occupancy<3>, dim3(grid), dim3(kBlock), 0, s, c, dilate, words); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_brick_flags(const float *sigma, int z0, int nz, int k, int nbl,
+                              uint32_t *flags, hipStream_t s) {
+  const int64_t nvox = (int64_t)nz * k * k;
+  int64_t blocks = (nvox + kBlock - 1) / kBlock;
+  const int grid = (int)(blocks < 65536 ? (blocks < 1 ? 1 : blocks) : 65536);
+  hipLaunchKernelGGL(k_brick_flags, dim3(grid), dim3(kBlock), 0, s, sigma, z0, nz, k, nbl, flags);
   return hipGetLastError();
 }
 

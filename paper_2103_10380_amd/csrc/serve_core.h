@@ -111,7 +111,9 @@ struct Config {
   uint64_t arena_bytes = 0;
   int max_inflight = 16;
   int queue_cap = 4096;
-  int step_tiles = 1 << 14;
+  // about 4M rays: several typical requests per step, so the per-step launch
+  // and synchronisation are amortised when the server is loaded
+  int step_tiles = 1 << 16;
 };
 
 class Core {

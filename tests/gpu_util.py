@@ -23,14 +23,15 @@ def gpu_available():
 
 
 def make_cache(sig, u, beta, *, storage="f32", pos_linear=False, dir_linear=True, brick=8,
-               in_box=False, bg=(1.0, 1.0, 1.0)):
+               in_box=False, bg=(1.0, 1.0, 1.0), sparse=False):
     import paper_2103_10380_amd as fn
     k, D = sig.shape[0], u.shape[-2]
     l = beta.shape[0]
     desc = fn.make_desc(k, D, l, storage=storage,
                         pos_interp=fn.LINEAR if pos_linear else fn.NEAREST,
                         dir_interp=fn.LINEAR if dir_linear else fn.NEAREST, brick=brick,
-                        sample_mode=fn.IN_BOX if in_box else fn.NEAR_FAR, background=bg)
+                        sample_mode=fn.IN_BOX if in_box else fn.NEAR_FAR, background=bg,
+                        sparse=sparse)
     return fn.Cache.create(desc, sig, u, beta)
 
 

@@ -52,13 +52,20 @@ def test_bad_descriptors_rejected_without_device(L):
     from paper_2103_10380_amd._lib import Desc
     h = ctypes.c_void_p()
     for kw in (dict(k=0), dict(D=0), dict(D=17), dict(l=0), dict(brick=3), dict(brick=16, k=24),
-               dict(storage=7)):
+               dict(storage=7),
+               # brick-sparse caches: nearest lookups, brick 8, k a multiple of 8
+               dict(sparse=True, pos_interp=fn.LINEAR), dict(sparse=True, brick=16),
+               dict(sparse=True, brick=0), dict(sparse=True, k=36, brick=4)):
         args = dict(k=kw.pop("k", 32), D=kw.pop("D", 8), l=kw.pop("l", 8))
         d = fn.make_desc(args["k"], args["D"], args["l"], **kw)
         st = L.fastnerf_cache_create_empty(ctypes.byref(d), ctypes.c_void_p(1), None,
                                            ctypes.byref(h))
         assert st == -1, kw
         assert L.fastnerf_last_error()
+    d = fn.make_desc(32, 8, 8)
+    d.sparse = 2
+    assert L.fastnerf_cache_create_empty(ctypes.byref(d), ctypes.c_void_p(1), None,
+                                         ctypes.byref(h)) == -1
     st = L.fastnerf_cache_create_empty(None, None, None, ctypes.byref(h))
     assert st == -1
     d = Desc()
