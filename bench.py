@@ -177,11 +177,17 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs
         f32["checked"] += int((~unchecked).sum())
         if (~unchecked).any():
             f32["worst"] = max(f32["worst"], float(err[~unchecked].max()))
+        # the other formats over the same checked pixels (an unchecked pixel
+        # has no admissible oracle result to compare with)
+        chk = ~unchecked
         for st, acc in other.items():
-            g = outs[st][vi].reshape(-1, 4)[idx].cpu().numpy().astype(np.float64)
-            err, _ = oracle.matches(g, r, 1.0)
+            g = outs[st][vi].reshape(-1, 4)[idx].cpu().numpy().astype(np.float64)[chk]
+            if not len(g):
+                continue
+            rc = {key: r[key][chk] for key in ("cand", "ncand")}
+            err, _ = oracle.matches(g, rc, 1.0)
             acc["worst"] = max(acc["worst"], float(err.max()))
-            acc["se"] += float(np.sum((g[:, :3] - r["rgba"][:, :3]) ** 2))
+            acc["se"] += float(np.sum((g[:, :3] - r["rgba"][chk][:, :3]) ** 2))
             acc["n"] += g.shape[0] * 3
         del r
         if t_cpu >= seconds:
