@@ -382,3 +382,57 @@ def paper_orbit(n=40, W=800, H=800, r=4.0, el=0.5):
     """n views on an orbit at radius r, elevation el, az = 2 pi v / n + 0.1,
     focal 1.2 W; samples span [0, 100] clipped to the box."""
     return [orbit_view(r, 2 * math.pi * v / n + 0.1, el, W, H, 0.0, 100.0) for v in range(n)]
+
+
+# --------------------------------------------------------------------------- networks
+
+@dataclasses.dataclass(frozen=True)
+class MlpSpec:
+    """Shapes of the factorised networks (Sec. 4: an 8-layer, 384-wide position
+    network and a 4-layer, 128-wide direction network, Fourier features with
+    L = 10 and L = 4 frequencies) and the seed of their random weights."""
+    D: int = 8
+    pos_hidden: int = 384
+    pos_layers: int = 8
+    pos_skip: int = 5
+    pos_freqs: int = 10
+    dir_hidden: int = 128
+    dir_layers: int = 4
+    dir_freqs: int = 4
+    seed: int = 7
+
+
+def _layer_shapes(n_in, hidden, layers, skip, n_out):
+    shapes = []
+    for i in range(layers):
+        fan_in = n_in if i == 0 else hidden + (n_in if i == skip else 0)
+        shapes.append((fan_in, hidden))
+    shapes.append((hidden, n_out))
+    return shapes
+
+
+def mlp_shapes(spec: MlpSpec):
+    """(pos, dir) lists of weight shapes [fan_in, fan_out], output layer last."""
+    pos = _layer_shapes(6 * spec.pos_freqs, spec.pos_hidden, spec.pos_layers, spec.pos_skip,
+                        1 + 3 * spec.D)
+    dirs = _layer_shapes(6 * spec.dir_freqs, spec.dir_hidden, spec.dir_layers, -1, spec.D)
+    return pos, dirs
+
+
+def mlp_weights(spec: MlpSpec):
+    """Random weights of both networks: dict(pos=[(W, b), ...], dir=[...]) as
+    float32, W [fan_in, fan_out]. W ~ U(-a, a) with a = sqrt(6 / fan_in) (the
+    variance-preserving uniform draw for ReLU layers), rounded to the nearest
+    binary16 value so that every consumer sees the same weights; b ~ U(-0.1,
+    0.1) in float32. Draw order: position layers, then direction layers."""
+    rng = np.random.default_rng(spec.seed)
+    out = {}
+    for name, shapes in zip(("pos", "dir"), mlp_shapes(spec)):
+        layers = []
+        for fan_in, fan_out in shapes:
+            a = math.sqrt(6.0 / fan_in)
+            W = rng.uniform(-a, a, (fan_in, fan_out)).astype(np.float16).astype(np.float32)
+            b = rng.uniform(-0.1, 0.1, fan_out).astype(np.float32)
+            layers.append((W, b))
+        out[name] = layers
+    return out
