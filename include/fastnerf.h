@@ -204,6 +204,63 @@ fastnerf_status fastnerf_server_stats(fastnerf_server server, uint64_t *steps,
 /* Drains running work, cancels queued requests, frees everything. */
 fastnerf_status fastnerf_server_destroy(fastnerf_server server);
 
+/* ---------------------------------------------------------------- cache bake */
+
+/* Evaluates FastNeRF's two networks where the caches sample them (Sec. 3.2,
+ * Eqs. 3-4; Sec. 3.3): the position network F_pos at the voxel centres of a
+ * k^3 grid, the direction network F_dir at the (theta, phi) cell centres of an
+ * l x l grid. Matrix products run on the matrix cores in binary16 with FP32
+ * accumulation; the Fourier features are computed in FP64 and rounded to
+ * binary16, every hidden activation is rounded to binary16, biases and the
+ * output layer's activations are FP32.
+ *
+ * Network (Sec. 4 and its readings): features of a point x (3 coordinates):
+ * feature 6j + a = sin(2^j pi x_a), feature 6j + 3 + a = cos(2^j pi x_a),
+ * j < L; then `layers` fully connected ReLU layers of `hidden` units (layer
+ * `skip` takes [previous activation, features], hidden units first), then a
+ * linear output layer. Position outputs: sigma = max(o_0, 0), u[d][c] =
+ * sigmoid(o_{1+3d+c}). Direction outputs: beta = softmax(o) over D. */
+typedef struct fastnerf_mlp_s *fastnerf_mlp;
+
+typedef struct {
+  int32_t D;          /* components, 1..16 */
+  int32_t pos_hidden; /* hidden width of F_pos: a multiple of 32 in [32, 384] */
+  int32_t pos_layers; /* hidden layers of F_pos, 1..16 */
+  int32_t pos_skip;   /* hidden layer in [1, pos_layers) that also takes the features; -1: none */
+  int32_t pos_freqs;  /* Fourier frequencies L of the position features, 1..10 */
+  int32_t dir_hidden; /* hidden width of F_dir: a multiple of 32 in [32, 384] */
+  int32_t dir_layers; /* hidden layers of F_dir, 1..16 */
+  int32_t dir_freqs;  /* Fourier frequencies of the direction features, 1..10 */
+} fastnerf_mlp_desc;
+
+/* Copies both networks' parameters to the current device. pos_params and
+ * dir_params are host FP32 arrays holding, for every layer in order (hidden
+ * layers, then the output layer), W[fan_in][fan_out] row-major then
+ * b[fan_out]. Fan-ins: 6L for layer 0, hidden + 6L for the skip layer, hidden
+ * otherwise; fan-outs: hidden, then 1 + 3D (F_pos) or D (F_dir). Weights are
+ * rounded to binary16 (nearest even); biases stay FP32. EINVAL on a bad
+ * descriptor or a non-finite parameter. */
+fastnerf_status fastnerf_mlp_create(const fastnerf_mlp_desc *desc, const float *pos_params,
+                                    const float *dir_params, fastnerf_mlp *out);
+/* Number of FP32 values fastnerf_mlp_create reads from pos_params and
+ * dir_params for this descriptor (-1 if the descriptor is invalid). */
+int64_t fastnerf_mlp_param_count(const fastnerf_mlp_desc *desc, int32_t which /* 0 pos, 1 dir */);
+/* F_pos at the centres of voxels z0..z0+nz-1 of a k^3 grid over the box
+ * (voxel (x, y, z) at bbox_min + (i + 1/2) (bbox_max - bbox_min) / k per
+ * axis). Writes device FP32 arrays laid out like a cache slab:
+ * sigma[nz][k][k], u[nz][k][k][D][3] (x fastest), ready for
+ * fastnerf_cache_upload_slab. Enqueued on `stream`. k in [1, 4096]. */
+fastnerf_status fastnerf_bake_position(fastnerf_mlp mlp, int32_t k, const float bbox_min[3],
+                                       const float bbox_max[3], int32_t z0, int32_t nz,
+                                       float *sigma, float *u, hipStream_t stream);
+/* F_dir at the centres of an l x l direction grid (theta = (j + 1/2) pi / l,
+ * phi = (m + 1/2) 2 pi / l): device FP32 beta[l][l][D], the direction cache of
+ * fastnerf_cache_create. l in [1, 4096]. */
+fastnerf_status fastnerf_bake_direction(fastnerf_mlp mlp, int32_t l, float *beta,
+                                        hipStream_t stream);
+/* Waits for the network's outstanding bakes, then frees it. */
+fastnerf_status fastnerf_mlp_destroy(fastnerf_mlp mlp);
+
 /* Thread-local message for the last non-OK status of this thread. */
 const char *fastnerf_last_error(void);
 

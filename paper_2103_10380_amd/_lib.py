@@ -40,6 +40,13 @@ class Desc(ctypes.Structure):
                 ("sparse", ctypes.c_int32)]
 
 
+class MlpDesc(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("pos_hidden", ctypes.c_int32),
+                ("pos_layers", ctypes.c_int32), ("pos_skip", ctypes.c_int32),
+                ("pos_freqs", ctypes.c_int32), ("dir_hidden", ctypes.c_int32),
+                ("dir_layers", ctypes.c_int32), ("dir_freqs", ctypes.c_int32)]
+
+
 # every symbol the header declares: (name, restype, argtypes)
 _vp, _i32, _u64, _f32, _i64, _dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
                                      ctypes.c_float, ctypes.c_int64, ctypes.c_double)
@@ -71,6 +78,11 @@ SYMBOLS = {
     "fastnerf_server_stats": (_i32, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                      ctypes.POINTER(_u64)]),
     "fastnerf_server_destroy": (_i32, [_vp]),
+    "fastnerf_mlp_create": (_i32, [ctypes.POINTER(MlpDesc), _vp, _vp, _vp]),
+    "fastnerf_mlp_param_count": (_i64, [ctypes.POINTER(MlpDesc), _i32]),
+    "fastnerf_bake_position": (_i32, [_vp, _i32, _pf, _pf, _i32, _i32, _vp, _vp, _vp]),
+    "fastnerf_bake_direction": (_i32, [_vp, _i32, _vp, _vp]),
+    "fastnerf_mlp_destroy": (_i32, [_vp]),
     "fastnerf_last_error": (ctypes.c_char_p, []),
 }
 
@@ -352,3 +364,68 @@ def _copy_device(dst, src, nbytes):
     rc = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)
     if rc != 0:
         raise FastNeRFError(-3, f"hipMemcpy failed ({rc})")
+
+
+def mlp_desc(spec):
+    """MlpDesc from any object with the descriptor's field names (e.g. synth.MlpSpec)."""
+    d = MlpDesc()
+    for name, _ in MlpDesc._fields_:
+        setattr(d, name, int(getattr(spec, name)))
+    return d
+
+
+def _flat(layers):
+    return np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(),
+                                           np.asarray(b, np.float32).ravel()])
+                           for W, b in layers]).astype(np.float32)
+
+
+class Mlp:
+    """Both factorised networks on the device (fastnerf_mlp), for cache bakes."""
+
+    def __init__(self, spec, weights):
+        self.desc = mlp_desc(spec)
+        self.D = self.desc.D
+        pos, dirs = _flat(weights["pos"]), _flat(weights["dir"])
+        for arr, which in ((pos, 0), (dirs, 1)):
+            n = lib().fastnerf_mlp_param_count(ctypes.byref(self.desc), which)
+            if n != arr.size:
+                raise FastNeRFError(-1, f"network {which}: {arr.size} parameters, expected {n}")
+        h = ctypes.c_void_p()
+        check(lib().fastnerf_mlp_create(ctypes.byref(self.desc), _ptr(pos), _ptr(dirs),
+                                        ctypes.byref(h)))
+        self.handle = h
+
+    def bake_position(self, k, bbox_min, bbox_max, z0, nz, sigma=None, u=None, stream=None):
+        """sigma [nz,k,k], u [nz,k,k,D,3] device float32 tensors (new ones if None)."""
+        import torch
+        if sigma is None:
+            sigma = torch.empty((nz, k, k), dtype=torch.float32, device="cuda")
+        if u is None:
+            u = torch.empty((nz, k, k, self.D, 3), dtype=torch.float32, device="cuda")
+        lo, lp = _arr9(bbox_min, 3)
+        hi, hp = _arr9(bbox_max, 3)
+        check(lib().fastnerf_bake_position(self.handle, k, lp, hp, z0, nz, _ptr(sigma), _ptr(u),
+                                           _stream(stream)))
+        return sigma, u
+
+    def bake_direction(self, l, beta=None, stream=None):
+        """beta [l,l,D] device float32 tensor."""
+        import torch
+        if beta is None:
+            beta = torch.empty((l, l, self.D), dtype=torch.float32, device="cuda")
+        check(lib().fastnerf_bake_direction(self.handle, l, _ptr(beta), _stream(stream)))
+        return beta
+
+    def destroy(self):
+        if self.handle:
+            check(lib().fastnerf_mlp_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.fastnerf_mlp_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

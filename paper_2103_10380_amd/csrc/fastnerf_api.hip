@@ -58,7 +58,7 @@ static int ilog2(uint64_t v) {
   return r;
 }
 
-static bool is_device_ptr(const void *p) {
+bool is_device_ptr(const void *p) {
   hipPointerAttribute_t attr;
   hipError_t e = hipPointerGetAttributes(&attr, p);
   if (e != hipSuccess) {

@@ -1,0 +1,429 @@
+// Cache bake: FastNeRF's position and direction networks (Sec. 3.2, Eqs. 3-4)
+// evaluated at the points the caches sample (Sec. 3.3), on the matrix cores.
+//
+// A workgroup of four waves takes 128 points through every layer. The
+// activations stay in LDS as binary16 (128 rows x 384 columns plus the Fourier
+// features), the weights stream from L2 as ready-made MFMA B fragments, and
+// every layer is one 128 x n x k product by v_mfma_f32_32x32x16_f16 (binary16
+// inputs, FP32 accumulation): wave w owns the output column blocks w, w+4,
+// w+8 of 32 columns for all 128 rows (four row blocks). After a layer the
+// accumulators take the bias and the ReLU and go back to LDS as binary16; the
+// output layer's raw values go to LDS as FP32 and the heads (relu / sigmoid /
+// softmax) are applied while they are written out.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "fastnerf.h"
+#include "fastnerf_internal.h"
+
+namespace fnr {
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kRows = 128;                  // points per workgroup
+constexpr int kWaves = 4;
+constexpr int kThreads = kWaves * 64;
+constexpr int kMaxHidden = 384;
+constexpr int kActStride = kMaxHidden + 8;  // halves per activation row (16-byte aligned rows)
+constexpr int kFeat = 64;                   // feature columns: 6L <= 60, zero padded
+constexpr int kFeatStride = kFeat + 8;
+constexpr int kMaxBlk = 3;                  // 32-column output blocks per wave (384 / 32 / 4)
+constexpr int kMaxLayers = 16;
+constexpr int kRawStride = 65;              // floats per row of the output layer's raw values
+
+struct BakeLayer {
+  const half8 *w;  // B fragments [k-step][block][lane]: 8 halves of rows 16s + 8(lane/32) + i
+  const float *b;  // bias, nblk * 32 floats (zero past the fan-out)
+  int ks_h;        // k-steps (16 inputs each) over the previous activation
+  int ks_f;        // then k-steps over the features (layer 0 and the skip layer)
+  int nblk;        // 32-column output blocks
+};
+
+struct BakeArgs {
+  BakeLayer L[kMaxLayers + 1];  // hidden layers, then the output layer
+  int nlayers;
+  int freqs;
+  int D;
+  int64_t npoints;
+  int k, z0;                    // position grid: voxel centres of layers z0..
+  double lo[3], h[3];
+  int l;                        // direction grid
+  float *out0, *out1;           // sigma, u | beta
+};
+
+// Sample point q: a voxel centre (x fastest) or a direction-cell centre
+// (theta row, phi column), in FP64.
+template <int MODE>
+__device__ inline void point_of(const BakeArgs &a, int64_t q, double x[3]) {
+  if (MODE == 0) {
+    const int64_t kk = (int64_t)a.k * a.k;
+    const int64_t iz = q / kk, rem = q - iz * kk;
+    const int64_t iy = rem / a.k, ix = rem - iy * a.k;
+    x[0] = a.lo[0] + ((double)ix + 0.5) * a.h[0];
+    x[1] = a.lo[1] + ((double)iy + 0.5) * a.h[1];
+    x[2] = a.lo[2] + ((double)(a.z0 + iz) + 0.5) * a.h[2];
+  } else {
+    const int64_t j = q / a.l, m = q - j * a.l;
+    const double th = ((double)j + 0.5) * M_PI / a.l;
+    const double ph = ((double)m + 0.5) * 2.0 * M_PI / a.l;
+    x[0] = sin(th) * cos(ph);
+    x[1] = sin(th) * sin(ph);
+    x[2] = cos(th);
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_bake(BakeArgs a) {
+  __shared__ __attribute__((aligned(16))) _Float16 act[kRows * kActStride];
+  __shared__ __attribute__((aligned(16))) _Float16 feat[kRows * kFeatStride];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * kRows;
+
+  // Fourier features: two threads per row, 32 columns each; the argument
+  // 2^j x is exact, sin(pi .) and cos(pi .) in FP64, rounded to binary16.
+  {
+    const int r = tid >> 1, c0 = (tid & 1) * 32;
+    int64_t q = row0 + r;
+    if (q >= a.npoints) q = a.npoints - 1;  // rows past the end repeat the last point
+    double x[3];
+    point_of<MODE>(a, q, x);
+    const int nf = 6 * a.freqs;
+    for (int cc = 0; cc < 32; ++cc) {
+      const int c = c0 + cc;
+      float v = 0.0f;
+      if (c < nf) {
+        const int j = c / 6, rem = c - 6 * j, ax = rem % 3;
+        const double arg = ldexp(x[ax], j);
+        v = (float)(rem < 3 ? sinpi(arg) : cospi(arg));
+      }
+      feat[r * kFeatStride + c] = (_Float16)v;
+    }
+  }
+  __syncthreads();
+
+  const int mrow = lane & 31, kq = (lane >> 5) * 8;
+  for (int li = 0; li <= a.nlayers; ++li) {
+    const BakeLayer Ly = a.L[li];
+    f32x16 acc[4][kMaxBlk];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int j = 0; j < kMaxBlk; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[mb][j][r] = 0.0f;
+    const int ks = Ly.ks_h + Ly.ks_f;
+    // B fragments of step s + 1 are requested before step s's products
+    half8 B[kMaxBlk], Bn[kMaxBlk];
+#pragma unroll
+    for (int j = 0; j < kMaxBlk; ++j) {
+      const int nb = wave + kWaves * j;
+      B[j] = nb < Ly.nblk ? Ly.w[(size_t)nb * 64 + lane] : half8{};
+    }
+    for (int s = 0; s < ks; ++s) {
+#pragma unroll
+      for (int j = 0; j < kMaxBlk; ++j) {
+        const int nb = wave + kWaves * j;
+        Bn[j] = (nb < Ly.nblk && s + 1 < ks) ? Ly.w[((size_t)(s + 1) * Ly.nblk + nb) * 64 + lane]
+                                              : half8{};
+      }
+      const bool from_act = s < Ly.ks_h;
+      const _Float16 *src = from_act ? act + 16 * s : feat + 16 * (s - Ly.ks_h);
+      const int stride = from_act ? kActStride : kFeatStride;
+      half8 A[4];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+        A[mb] = *reinterpret_cast<const half8 *>(src + (32 * mb + mrow) * stride + kq);
+#pragma unroll
+      for (int j = 0; j < kMaxBlk; ++j) {
+        if (wave + kWaves * j < Ly.nblk) {
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb)
+            acc[mb][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[mb], B[j], acc[mb][j], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kMaxBlk; ++j) B[j] = Bn[j];
+    }
+    __syncthreads();  // every wave has read this layer's input
+    // accumulator element r of lane l: row 8(r/4) + 4(l/32) + r%4 of the
+    // block, column l%32
+    if (li < a.nlayers) {
+#pragma unroll
+      for (int j = 0; j < kMaxBlk; ++j) {
+        const int nb = wave + kWaves * j;
+        if (nb >= Ly.nblk) continue;
+        const int n = 32 * nb + mrow;
+        const float bias = Ly.b[n];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int m = 32 * mb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            act[m * kActStride + n] = (_Float16)fmaxf(acc[mb][j][r] + bias, 0.0f);
+          }
+      }
+      __syncthreads();
+    } else {
+      float *raw = reinterpret_cast<float *>(act);
+#pragma unroll
+      for (int j = 0; j < kMaxBlk; ++j) {
+        const int nb = wave + kWaves * j;
+        if (nb >= Ly.nblk) continue;
+        const int n = 32 * nb + mrow;
+        const float bias = Ly.b[n];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int m = 32 * mb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            raw[m * kRawStride + n] = acc[mb][j][r] + bias;
+          }
+      }
+      __syncthreads();
+      const int D = a.D;
+      if (MODE == 0) {
+        const int nout = 1 + 3 * D;
+        for (int e = tid; e < kRows * nout; e += kThreads) {
+          const int r = e / nout, c = e - r * nout;
+          const int64_t q = row0 + r;
+          if (q >= a.npoints) continue;
+          const float v = raw[r * kRawStride + c];
+          if (c == 0)
+            a.out0[q] = fmaxf(v, 0.0f);
+          else
+            a.out1[q * (3 * D) + (c - 1)] = 1.0f / (1.0f + expf(-v));
+        }
+      } else if (tid < kRows) {
+        const int64_t q = row0 + tid;
+        if (q < a.npoints) {
+          const float *o = raw + tid * kRawStride;
+          float mx = o[0];
+          for (int d = 1; d < D; ++d) mx = fmaxf(mx, o[d]);
+          float sum = 0.0f;
+          for (int d = 0; d < D; ++d) sum += expf(o[d] - mx);
+          const float inv = 1.0f / sum;
+          for (int d = 0; d < D; ++d) a.out0[q * D + d] = expf(o[d] - mx) * inv;
+        }
+      }
+    }
+  }
+}
+
+bool valid_desc(const fastnerf_mlp_desc *d) {
+  if (!d) return false;
+  auto width_ok = [](int h) { return h >= 32 && h <= kMaxHidden && h % 32 == 0; };
+  return d->D >= 1 && d->D <= 16 && width_ok(d->pos_hidden) && width_ok(d->dir_hidden) &&
+         d->pos_layers >= 1 && d->pos_layers <= kMaxLayers && d->dir_layers >= 1 &&
+         d->dir_layers <= kMaxLayers &&
+         (d->pos_skip == -1 || (d->pos_skip >= 1 && d->pos_skip < d->pos_layers)) &&
+         d->pos_freqs >= 1 && d->pos_freqs <= 10 && d->dir_freqs >= 1 && d->dir_freqs <= 10;
+}
+
+struct NetShape {
+  int layers, hidden, skip, freqs, nout;
+};
+
+NetShape net_shape(const fastnerf_mlp_desc *d, int which) {
+  return which == 0 ? NetShape{d->pos_layers, d->pos_hidden, d->pos_skip, d->pos_freqs, 1 + 3 * d->D}
+                    : NetShape{d->dir_layers, d->dir_hidden, -1, d->dir_freqs, d->D};
+}
+
+// Fan-in of the previous activation and whether the layer takes the features.
+void layer_inputs(const NetShape &n, int i, int *hh, bool *feats, int *fan_out) {
+  *hh = i == 0 ? 0 : n.hidden;
+  *feats = i == 0 || i == n.skip;
+  *fan_out = i == n.layers ? n.nout : n.hidden;
+}
+
+int64_t param_count(const NetShape &n) {
+  int64_t c = 0;
+  for (int i = 0; i <= n.layers; ++i) {
+    int hh, fo;
+    bool f;
+    layer_inputs(n, i, &hh, &f, &fo);
+    c += (int64_t)(hh + (f ? 6 * n.freqs : 0)) * fo + fo;
+  }
+  return c;
+}
+
+}  // namespace
+}  // namespace fnr
+
+using namespace fnr;
+
+struct fastnerf_mlp_s {
+  fastnerf_mlp_desc desc;
+  int device = 0;
+  uint8_t *buf = nullptr;
+  fnr::BakeLayer net[2][fnr::kMaxLayers + 1];
+  hipEvent_t last_use = nullptr;
+};
+
+extern "C" int64_t fastnerf_mlp_param_count(const fastnerf_mlp_desc *desc, int32_t which) {
+  if (!valid_desc(desc) || (which != 0 && which != 1)) return -1;
+  return param_count(net_shape(desc, which));
+}
+
+extern "C" fastnerf_status fastnerf_mlp_create(const fastnerf_mlp_desc *desc,
+                                               const float *pos_params, const float *dir_params,
+                                               fastnerf_mlp *out) {
+  if (!out) return fail(FASTNERF_EINVAL, "null out");
+  *out = nullptr;
+  if (!valid_desc(desc)) return fail(FASTNERF_EINVAL, "invalid network descriptor");
+  if (!pos_params || !dir_params) return fail(FASTNERF_EINVAL, "null parameters");
+  if (is_device_ptr(pos_params) || is_device_ptr(dir_params))
+    return fail(FASTNERF_EINVAL, "network parameters must be host arrays");
+  const float *params[2] = {pos_params, dir_params};
+  // pack every layer: B fragments (binary16) then the padded bias, each
+  // 256-byte aligned, both networks in one device buffer
+  std::vector<uint8_t> host;
+  struct Off {
+    size_t w, b;
+  };
+  std::vector<Off> offs[2];
+  int shape_ks[2][kMaxLayers + 1][3];
+  for (int which = 0; which < 2; ++which) {
+    const NetShape n = net_shape(desc, which);
+    const int64_t count = param_count(n);
+    for (int64_t i = 0; i < count; ++i)
+      if (!isfinite(params[which][i])) return fail(FASTNERF_EINVAL, "non-finite parameter");
+    const float *p = params[which];
+    for (int i = 0; i <= n.layers; ++i) {
+      int hh, fo;
+      bool f;
+      layer_inputs(n, i, &hh, &f, &fo);
+      const int fan_in = hh + (f ? 6 * n.freqs : 0);
+      const float *W = p, *b = p + (size_t)fan_in * fo;
+      p = b + fo;
+      const int ks_h = hh / 16, ks_f = f ? kFeat / 16 : 0, ks = ks_h + ks_f;
+      const int nblk = (fo + 31) / 32;
+      shape_ks[which][i][0] = ks_h;
+      shape_ks[which][i][1] = ks_f;
+      shape_ks[which][i][2] = nblk;
+      Off o;
+      o.w = (host.size() + 255) & ~(size_t)255;
+      const size_t wbytes = (size_t)ks * nblk * 64 * 16;
+      o.b = (o.w + wbytes + 255) & ~(size_t)255;
+      host.resize(o.b + (size_t)nblk * 32 * 4, 0);
+      _Float16 *wf = reinterpret_cast<_Float16 *>(host.data() + o.w);
+      for (int s = 0; s < ks; ++s)
+        for (int nb = 0; nb < nblk; ++nb)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e) {
+              const int kk = 16 * s + 8 * (l / 32) + e;  // input index of the padded layer
+              int row = -1;
+              if (s < ks_h) {
+                row = kk;
+              } else {
+                const int fi = kk - 16 * ks_h;  // feature index
+                if (fi < 6 * n.freqs) row = hh + fi;
+              }
+              const int col = 32 * nb + (l & 31);
+              const float v = (row >= 0 && col < fo) ? W[(size_t)row * fo + col] : 0.0f;
+              wf[(((size_t)s * nblk + nb) * 64 + l) * 8 + e] = (_Float16)v;
+            }
+      memcpy(host.data() + o.b, b, (size_t)fo * 4);
+      offs[which].push_back(o);
+    }
+  }
+  fastnerf_mlp_s *m = new (std::nothrow) fastnerf_mlp_s();
+  if (!m) return fail(FASTNERF_ENOMEM, "host allocation");
+  m->desc = *desc;
+  (void)hipGetDevice(&m->device);
+  hipError_t e = hipMalloc(&m->buf, host.size());
+  if (e == hipSuccess) e = hipMemcpy(m->buf, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->last_use, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    fastnerf_status st = hip_fail(e, "network upload");
+    fastnerf_mlp_destroy(m);
+    return st;
+  }
+  for (int which = 0; which < 2; ++which)
+    for (size_t i = 0; i < offs[which].size(); ++i) {
+      BakeLayer &L = m->net[which][i];
+      L.w = reinterpret_cast<const half8 *>(m->buf + offs[which][i].w);
+      L.b = reinterpret_cast<const float *>(m->buf + offs[which][i].b);
+      L.ks_h = shape_ks[which][i][0];
+      L.ks_f = shape_ks[which][i][1];
+      L.nblk = shape_ks[which][i][2];
+    }
+  *out = m;
+  return FASTNERF_OK;
+}
+
+static fastnerf_status launch_bake(fastnerf_mlp m, int which, BakeArgs &a, hipStream_t s) {
+  const fastnerf_mlp_desc &d = m->desc;
+  const NetShape n = net_shape(&d, which);
+  for (int i = 0; i <= n.layers; ++i) a.L[i] = m->net[which][i];
+  a.nlayers = n.layers;
+  a.freqs = n.freqs;
+  a.D = d.D;
+  const int64_t blocks = (a.npoints + kRows - 1) / kRows;
+  if (blocks > 0x7fffffffLL) return fail(FASTNERF_EINVAL, "too many points in one bake");
+  if (which == 0)
+    hipLaunchKernelGGL(k_bake<0>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_bake<1>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "bake launch");
+  e = hipEventRecord(m->last_use, s);
+  if (e != hipSuccess) return hip_fail(e, "bake event");
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_bake_position(fastnerf_mlp m, int32_t k,
+                                                  const float bbox_min[3],
+                                                  const float bbox_max[3], int32_t z0, int32_t nz,
+                                                  float *sigma, float *u, hipStream_t stream) {
+  if (!m) return fail(FASTNERF_EINVAL, "null network");
+  if (k < 1 || k > 4096) return fail(FASTNERF_EINVAL, "k = %d outside [1, 4096]", k);
+  if (!bbox_min || !bbox_max) return fail(FASTNERF_EINVAL, "null bounding box");
+  for (int ax = 0; ax < 3; ++ax)
+    if (!isfinite(bbox_min[ax]) || !isfinite(bbox_max[ax]) || !(bbox_min[ax] < bbox_max[ax]))
+      return fail(FASTNERF_EINVAL, "bad bounding box");
+  if (z0 < 0 || nz < 1 || z0 + nz > k)
+    return fail(FASTNERF_EINVAL, "slab [%d, %d) outside [0, %d)", z0, z0 + nz, k);
+  if (!sigma || !u || !is_device_ptr(sigma) || !is_device_ptr(u))
+    return fail(FASTNERF_EINVAL, "sigma and u must be device arrays");
+  BakeArgs a;
+  memset(&a, 0, sizeof a);
+  a.npoints = (int64_t)nz * k * k;
+  a.k = k;
+  a.z0 = z0;
+  for (int ax = 0; ax < 3; ++ax) {
+    a.lo[ax] = bbox_min[ax];
+    a.h[ax] = ((double)bbox_max[ax] - (double)bbox_min[ax]) / k;
+  }
+  a.out0 = sigma;
+  a.out1 = u;
+  return launch_bake(m, 0, a, stream);
+}
+
+extern "C" fastnerf_status fastnerf_bake_direction(fastnerf_mlp m, int32_t l, float *beta,
+                                                   hipStream_t stream) {
+  if (!m) return fail(FASTNERF_EINVAL, "null network");
+  if (l < 1 || l > 4096) return fail(FASTNERF_EINVAL, "l = %d outside [1, 4096]", l);
+  if (!beta || !is_device_ptr(beta)) return fail(FASTNERF_EINVAL, "beta must be a device array");
+  BakeArgs a;
+  memset(&a, 0, sizeof a);
+  a.npoints = (int64_t)l * l;
+  a.l = l;
+  a.out0 = beta;
+  return launch_bake(m, 1, a, stream);
+}
+
+extern "C" fastnerf_status fastnerf_mlp_destroy(fastnerf_mlp m) {
+  if (!m) return fail(FASTNERF_EINVAL, "null network");
+  if (m->last_use) {
+    (void)hipEventSynchronize(m->last_use);
+    (void)hipEventDestroy(m->last_use);
+  }
+  if (m->buf) (void)hipFree(m->buf);
+  delete m;
+  return FASTNERF_OK;
+}

@@ -32,6 +32,7 @@ namespace fnr {
 
 fastnerf_status fail(fastnerf_status st, const char *fmt, ...);
 fastnerf_status hip_fail(hipError_t e, const char *what);
+bool is_device_ptr(const void *p);
 
 struct StreamState;
 fastnerf_status stream_state(hipStream_t s, StreamState **out);

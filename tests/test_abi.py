@@ -80,3 +80,28 @@ def test_null_handles_rejected(L):
     assert L.fastnerf_cache_finalize(None, None) == -1
     v = ctypes.c_uint64()
     assert L.fastnerf_cache_bytes(None, ctypes.byref(v)) == -1
+
+
+def test_mlp_descriptors_checked_without_device(L):
+    import synth
+    from paper_2103_10380_amd import _lib
+    d = _lib.mlp_desc(synth.MlpSpec())
+    # 60x384 + 4 x 384x384 + 444x384 + 2 x 384x384 + 384x25, plus biases
+    n_pos = 60 * 384 + 6 * 384 * 384 + 444 * 384 + 384 * 25 + 8 * 384 + 25
+    assert L.fastnerf_mlp_param_count(ctypes.byref(d), 0) == n_pos
+    assert L.fastnerf_mlp_param_count(ctypes.byref(d), 1) == 24 * 128 + 3 * 128 * 128 + \
+        128 * 8 + 4 * 128 + 8
+    assert L.fastnerf_mlp_param_count(ctypes.byref(d), 2) == -1
+    w = synth.mlp_weights(synth.MlpSpec())
+    assert sum(W.size + b.size for W, b in w["pos"]) == n_pos
+    h = ctypes.c_void_p()
+    for field, bad in (("D", 0), ("D", 17), ("pos_hidden", 48), ("pos_hidden", 416),
+                       ("dir_hidden", 0), ("pos_layers", 0), ("pos_layers", 17),
+                       ("pos_skip", 0), ("pos_skip", 8), ("pos_freqs", 11), ("dir_freqs", 0)):
+        d = _lib.mlp_desc(synth.MlpSpec())
+        setattr(d, field, bad)
+        assert L.fastnerf_mlp_param_count(ctypes.byref(d), 0) == -1, field
+        assert L.fastnerf_mlp_create(ctypes.byref(d), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                                     ctypes.byref(h)) == -1, field
+    assert L.fastnerf_mlp_destroy(None) == -1
+    assert L.fastnerf_bake_direction(None, 8, None, None) == -1
