@@ -3,13 +3,17 @@
 //
 // A workgroup of four waves takes 128 points through every layer. The
 // activations stay in LDS as binary16 (128 rows x 384 columns plus the Fourier
-// features), the weights stream from L2 as ready-made MFMA B fragments, and
+// features), the weights stream from L2 as ready-made MFMA fragments, and
 // every layer is one 128 x n x k product by v_mfma_f32_32x32x16_f16 (binary16
-// inputs, FP32 accumulation): wave w owns the output column blocks w, w+4,
-// w+8 of 32 columns for all 128 rows (four row blocks). After a layer the
-// accumulators take the bias and the ReLU and go back to LDS as binary16; the
-// output layer's raw values go to LDS as FP32 and the heads (relu / sigmoid /
-// softmax) are applied while they are written out.
+// inputs, FP32 accumulation) computed transposed, out^T = W^T act^T, so that
+// each lane's accumulators hold four consecutive output columns of one point
+// and go back to LDS as one 8-byte store. Wave w owns the output column
+// blocks w, w+4, w+8 of 32 columns for all 128 rows (four row blocks); the
+// weight fragments of the next two k-steps are in flight while two are
+// multiplied. After a layer the accumulators take the bias and the ReLU and
+// go back to LDS as binary16; the output layer's raw values go to LDS as FP32
+// and the heads (relu / sigmoid / softmax) are applied while they are
+// written out.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -34,10 +38,10 @@ constexpr int kFeat = 64;                   // feature columns: 6L <= 60, zero p
 constexpr int kFeatStride = kFeat + 8;
 constexpr int kMaxBlk = 3;                  // 32-column output blocks per wave (384 / 32 / 4)
 constexpr int kMaxLayers = 16;
-constexpr int kRawStride = 65;              // floats per row of the output layer's raw values
+constexpr int kRawStride = 68;              // floats per row of the output layer's raw values
 
 struct BakeLayer {
-  const half8 *w;  // B fragments [k-step][block][lane]: 8 halves of rows 16s + 8(lane/32) + i
+  const half8 *w;  // fragments [k-step][block][lane]: W rows 16s + 8(lane/32) + i, column lane%32
   const float *b;  // bias, nblk * 32 floats (zero past the fan-out)
   int ks_h;        // k-steps (16 inputs each) over the previous activation
   int ks_f;        // then k-steps over the features (layer 0 and the skip layer)
@@ -77,6 +81,88 @@ __device__ inline void point_of(const BakeArgs &a, int64_t q, double x[3]) {
   }
 }
 
+// Activation fragments of k-steps s, s+1 for the four row blocks.
+__device__ __forceinline__ void load_act(const BakeLayer &Ly, const _Float16 *act,
+                                         const _Float16 *feat, int s, int mrow, int kq,
+                                         half8 (&a0)[4], half8 (&a1)[4]) {
+  const bool from_act = s < Ly.ks_h;
+  const _Float16 *src = from_act ? act + 16 * s : feat + 16 * (s - Ly.ks_h);
+  const int stride = from_act ? kActStride : kFeatStride;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const _Float16 *p = src + (32 * mb + mrow) * stride + kq;
+    a0[mb] = *reinterpret_cast<const half8 *>(p);
+    a1[mb] = *reinterpret_cast<const half8 *>(p + 16);
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void load_w(const half8 *const (&wp)[NB], size_t sstride, int s,
+                                       half8 (&b0)[NB], half8 (&b1)[NB]) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    b0[j] = wp[j][(size_t)s * sstride];
+    b1[j] = wp[j][(size_t)(s + 1) * sstride];
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void mfma_pair(const half8 (&b0)[NB], const half8 (&b1)[NB],
+                                          const half8 (&a0)[4], const half8 (&a1)[4],
+                                          f32x16 (&acc)[4][kMaxBlk]) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+      acc[mb][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(b0[j], a0[mb], acc[mb][j], 0, 0, 0);
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+      acc[mb][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(b1[j], a1[mb], acc[mb][j], 0, 0, 0);
+}
+
+// acc[mb][j] += (W block j of this wave)^T x (rows of block mb)^T over every
+// k-step of the layer; NB blocks per wave, no per-block conditions. Two sets
+// of weight and activation registers alternate (steps s, s+1 and s+2, s+3):
+// a set is reloaded, two steps ahead, as soon as its products are issued, so
+// a weight load has the other set's products to arrive. Loads past the last
+// step repeat the last pair: always valid addresses, never used.
+template <int NB>
+__device__ __forceinline__ void layer_gemm(const BakeLayer &Ly, const _Float16 *act,
+                                           const _Float16 *feat, int wave, int lane,
+                                           f32x16 (&acc)[4][kMaxBlk]) {
+  const int mrow = lane & 31, kq = (lane >> 5) * 8;
+  const int ks = Ly.ks_h + Ly.ks_f;  // even: hidden widths are multiples of 32
+  const int last = ks - 2;
+  const size_t sstride = (size_t)Ly.nblk * 64;
+  const half8 *wp[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) wp[j] = Ly.w + (size_t)(wave + kWaves * j) * 64 + lane;
+  half8 x0[NB], x1[NB], y0[NB], y1[NB], ax0[4], ax1[4], ay0[4], ay1[4];
+  load_w<NB>(wp, sstride, 0, x0, x1);
+  load_w<NB>(wp, sstride, min(2, last), y0, y1);
+  load_act(Ly, act, feat, 0, mrow, kq, ax0, ax1);
+  // both halves in every iteration, so that loads complete in one order on
+  // every path (the wait before a set's products then spares the other set)
+  int s = 0;
+  for (; s + 4 <= ks; s += 4) {
+    load_act(Ly, act, feat, min(s + 2, last), mrow, kq, ay0, ay1);
+    mfma_pair<NB>(x0, x1, ax0, ax1, acc);
+    load_w<NB>(wp, sstride, min(s + 4, last), x0, x1);
+    // neither the compiler nor the scheduler moves anything across: the
+    // reload stays between the two halves
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    load_act(Ly, act, feat, min(s + 4, last), mrow, kq, ax0, ax1);
+    mfma_pair<NB>(y0, y1, ay0, ay1, acc);
+    load_w<NB>(wp, sstride, min(s + 6, last), y0, y1);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (s < ks) mfma_pair<NB>(x0, x1, ax0, ax1, acc);  // ks = 4t + 2: the last pair
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kThreads) k_bake(BakeArgs a) {
   __shared__ __attribute__((aligned(16))) _Float16 act[kRows * kActStride];
@@ -106,7 +192,7 @@ __global__ void __launch_bounds__(kThreads) k_bake(BakeArgs a) {
   }
   __syncthreads();
 
-  const int mrow = lane & 31, kq = (lane >> 5) * 8;
+  const int mrow = lane & 31;
   for (int li = 0; li <= a.nlayers; ++li) {
     const BakeLayer Ly = a.L[li];
     f32x16 acc[4][kMaxBlk];
@@ -116,56 +202,38 @@ __global__ void __launch_bounds__(kThreads) k_bake(BakeArgs a) {
       for (int j = 0; j < kMaxBlk; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[mb][j][r] = 0.0f;
-    const int ks = Ly.ks_h + Ly.ks_f;
-    // B fragments of step s + 1 are requested before step s's products
-    half8 B[kMaxBlk], Bn[kMaxBlk];
-#pragma unroll
-    for (int j = 0; j < kMaxBlk; ++j) {
-      const int nb = wave + kWaves * j;
-      B[j] = nb < Ly.nblk ? Ly.w[(size_t)nb * 64 + lane] : half8{};
-    }
-    for (int s = 0; s < ks; ++s) {
-#pragma unroll
-      for (int j = 0; j < kMaxBlk; ++j) {
-        const int nb = wave + kWaves * j;
-        Bn[j] = (nb < Ly.nblk && s + 1 < ks) ? Ly.w[((size_t)(s + 1) * Ly.nblk + nb) * 64 + lane]
-                                              : half8{};
-      }
-      const bool from_act = s < Ly.ks_h;
-      const _Float16 *src = from_act ? act + 16 * s : feat + 16 * (s - Ly.ks_h);
-      const int stride = from_act ? kActStride : kFeatStride;
-      half8 A[4];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-        A[mb] = *reinterpret_cast<const half8 *>(src + (32 * mb + mrow) * stride + kq);
-#pragma unroll
-      for (int j = 0; j < kMaxBlk; ++j) {
-        if (wave + kWaves * j < Ly.nblk) {
-#pragma unroll
-          for (int mb = 0; mb < 4; ++mb)
-            acc[mb][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[mb], B[j], acc[mb][j], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < kMaxBlk; ++j) B[j] = Bn[j];
-    }
+    // blocks of this wave: w, w+4, w+8 below nblk (wave-uniform)
+    const int nmine = Ly.nblk > wave ? (Ly.nblk - wave + kWaves - 1) / kWaves : 0;
+    if (nmine >= 3)
+      layer_gemm<3>(Ly, act, feat, wave, lane, acc);
+    else if (nmine == 2)
+      layer_gemm<2>(Ly, act, feat, wave, lane, acc);
+    else if (nmine == 1)
+      layer_gemm<1>(Ly, act, feat, wave, lane, acc);
     __syncthreads();  // every wave has read this layer's input
-    // accumulator element r of lane l: row 8(r/4) + 4(l/32) + r%4 of the
-    // block, column l%32
+    // accumulator element r of lane l (transposed product): output column
+    // 8(r/4) + 4(l/32) + r%4 of the block, row l%32 of the row block
     if (li < a.nlayers) {
 #pragma unroll
       for (int j = 0; j < kMaxBlk; ++j) {
         const int nb = wave + kWaves * j;
         if (nb >= Ly.nblk) continue;
-        const int n = 32 * nb + mrow;
-        const float bias = Ly.b[n];
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+        for (int g = 0; g < 4; ++g) {
+          const int n = 32 * nb + 8 * g + 4 * (lane >> 5);
+          const float4 bias = *reinterpret_cast<const float4 *>(Ly.b + n);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int m = 32 * mb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            act[m * kActStride + n] = (_Float16)fmaxf(acc[mb][j][r] + bias, 0.0f);
+          for (int mb = 0; mb < 4; ++mb) {
+            const int m = 32 * mb + mrow;
+            typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+            half4 v;
+            v[0] = (_Float16)fmaxf(acc[mb][j][4 * g + 0] + bias.x, 0.0f);
+            v[1] = (_Float16)fmaxf(acc[mb][j][4 * g + 1] + bias.y, 0.0f);
+            v[2] = (_Float16)fmaxf(acc[mb][j][4 * g + 2] + bias.z, 0.0f);
+            v[3] = (_Float16)fmaxf(acc[mb][j][4 * g + 3] + bias.w, 0.0f);
+            *reinterpret_cast<half4 *>(act + m * kActStride + n) = v;
           }
+        }
       }
       __syncthreads();
     } else {
@@ -174,15 +242,21 @@ __global__ void __launch_bounds__(kThreads) k_bake(BakeArgs a) {
       for (int j = 0; j < kMaxBlk; ++j) {
         const int nb = wave + kWaves * j;
         if (nb >= Ly.nblk) continue;
-        const int n = 32 * nb + mrow;
-        const float bias = Ly.b[n];
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+        for (int g = 0; g < 4; ++g) {
+          const int n = 32 * nb + 8 * g + 4 * (lane >> 5);
+          const float4 bias = *reinterpret_cast<const float4 *>(Ly.b + n);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int m = 32 * mb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            raw[m * kRawStride + n] = acc[mb][j][r] + bias;
+          for (int mb = 0; mb < 4; ++mb) {
+            const int m = 32 * mb + mrow;
+            float4 v;
+            v.x = acc[mb][j][4 * g + 0] + bias.x;
+            v.y = acc[mb][j][4 * g + 1] + bias.y;
+            v.z = acc[mb][j][4 * g + 2] + bias.z;
+            v.w = acc[mb][j][4 * g + 3] + bias.w;
+            *reinterpret_cast<float4 *>(raw + m * kRawStride + n) = v;
           }
+        }
       }
       __syncthreads();
       const int D = a.D;
