@@ -413,7 +413,7 @@ def serving_scenes(fn):
     return caches
 
 
-def summarize_profile(paths, match=("k_render", "neg_kernel")):
+def summarize_profile(paths, match=("k_render", "k_bake", "neg_kernel")):
     """Compact text summary of rocprofv3 CSV output (kernel stats and counter
     collections): per-kernel calls and durations, per-dispatch counter means."""
     import csv

@@ -39,10 +39,11 @@ constexpr int kFeatStride = kFeat + 8;
 constexpr int kMaxBlk = 3;                  // 32-column output blocks per wave (384 / 32 / 4)
 constexpr int kMaxLayers = 16;
 constexpr int kRawStride = 68;              // floats per row of the output layer's raw values
+constexpr int kMaxBias = kMaxLayers * kMaxHidden + 64;  // floats of bias per network
 
 struct BakeLayer {
   const half8 *w;  // fragments [k-step][block][lane]: W rows 16s + 8(lane/32) + i, column lane%32
-  const float *b;  // bias, nblk * 32 floats (zero past the fan-out)
+  int boff;        // offset of the bias (nblk * 32 floats, zero past the fan-out) in the net's biases
   int ks_h;        // k-steps (16 inputs each) over the previous activation
   int ks_f;        // then k-steps over the features (layer 0 and the skip layer)
   int nblk;        // 32-column output blocks
@@ -50,6 +51,8 @@ struct BakeLayer {
 
 struct BakeArgs {
   BakeLayer L[kMaxLayers + 1];  // hidden layers, then the output layer
+  const float *bias;            // every layer's bias, in order
+  int nbias;
   int nlayers;
   int freqs;
   int D;
@@ -96,13 +99,16 @@ __device__ __forceinline__ void load_act(const BakeLayer &Ly, const _Float16 *ac
   }
 }
 
+// Weight fragments of k-steps s, s+1 of layer L for the wave's NB blocks.
 template <int NB>
-__device__ __forceinline__ void load_w(const half8 *const (&wp)[NB], size_t sstride, int s,
+__device__ __forceinline__ void load_w(const BakeLayer &L, int wave, int lane, int s,
                                        half8 (&b0)[NB], half8 (&b1)[NB]) {
+  const size_t stride = (size_t)L.nblk * 64;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    b0[j] = wp[j][(size_t)s * sstride];
-    b1[j] = wp[j][(size_t)(s + 1) * sstride];
+    const half8 *p = L.w + (size_t)s * stride + (size_t)(wave + kWaves * j) * 64 + lane;
+    b0[j] = p[0];
+    b1[j] = p[stride];
   }
 }
 
@@ -122,26 +128,41 @@ __device__ __forceinline__ void mfma_pair(const half8 (&b0)[NB], const half8 (&b
       acc[mb][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(b1[j], a1[mb], acc[mb][j], 0, 0, 0);
 }
 
+// The weight pair a set reloads at virtual step v: this layer's step v, or
+// past its end the next layer's step v - ks when the stream continues into
+// it (chain), else this layer's last pair again (a valid address,
+// never used).
+template <int NB>
+__device__ __forceinline__ void reload_w(const BakeLayer &Ly, const BakeLayer &next, bool chain,
+                                         int wave, int lane, int v, half8 (&b0)[NB],
+                                         half8 (&b1)[NB]) {
+  const int ks = Ly.ks_h + Ly.ks_f;
+  if (v < ks || !chain) {
+    load_w<NB>(Ly, wave, lane, min(v, ks - 2), b0, b1);
+  } else {
+    const int nks = next.ks_h + next.ks_f;
+    load_w<NB>(next, wave, lane, min(v - ks, nks - 2), b0, b1);
+  }
+}
+
 // acc[mb][j] += (W block j of this wave)^T x (rows of block mb)^T over every
 // k-step of the layer; NB blocks per wave, no per-block conditions. Two sets
 // of weight and activation registers alternate (steps s, s+1 and s+2, s+3):
 // a set is reloaded, two steps ahead, as soon as its products are issued, so
-// a weight load has the other set's products to arrive. Loads past the last
-// step repeat the last pair: always valid addresses, never used.
+// a weight load has the other set's products to arrive. On entry the sets
+// hold steps 0-3; with chain (next layer: same block count; ks a multiple of 4)
+// they hold the next layer's steps 0-3 on return, so its weights arrive
+// while this layer is written back.
 template <int NB>
-__device__ __forceinline__ void layer_gemm(const BakeLayer &Ly, const _Float16 *act,
-                                           const _Float16 *feat, int wave, int lane,
+__device__ __forceinline__ void layer_gemm(const BakeLayer &Ly, const BakeLayer &next,
+                                           bool chain, const _Float16 *act, const _Float16 *feat, int wave,
+                                           int lane, half8 (&x0)[NB], half8 (&x1)[NB],
+                                           half8 (&y0)[NB], half8 (&y1)[NB],
                                            f32x16 (&acc)[4][kMaxBlk]) {
   const int mrow = lane & 31, kq = (lane >> 5) * 8;
   const int ks = Ly.ks_h + Ly.ks_f;  // even: hidden widths are multiples of 32
   const int last = ks - 2;
-  const size_t sstride = (size_t)Ly.nblk * 64;
-  const half8 *wp[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) wp[j] = Ly.w + (size_t)(wave + kWaves * j) * 64 + lane;
-  half8 x0[NB], x1[NB], y0[NB], y1[NB], ax0[4], ax1[4], ay0[4], ay1[4];
-  load_w<NB>(wp, sstride, 0, x0, x1);
-  load_w<NB>(wp, sstride, min(2, last), y0, y1);
+  half8 ax0[4], ax1[4], ay0[4], ay1[4];
   load_act(Ly, act, feat, 0, mrow, kq, ax0, ax1);
   // both halves in every iteration, so that loads complete in one order on
   // every path (the wait before a set's products then spares the other set)
@@ -149,141 +170,202 @@ __device__ __forceinline__ void layer_gemm(const BakeLayer &Ly, const _Float16 *
   for (; s + 4 <= ks; s += 4) {
     load_act(Ly, act, feat, min(s + 2, last), mrow, kq, ay0, ay1);
     mfma_pair<NB>(x0, x1, ax0, ax1, acc);
-    load_w<NB>(wp, sstride, min(s + 4, last), x0, x1);
+    reload_w<NB>(Ly, next, chain, wave, lane, s + 4, x0, x1);
     // neither the compiler nor the scheduler moves anything across: the
     // reload stays between the two halves
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     load_act(Ly, act, feat, min(s + 4, last), mrow, kq, ax0, ax1);
     mfma_pair<NB>(y0, y1, ay0, ay1, acc);
-    load_w<NB>(wp, sstride, min(s + 6, last), y0, y1);
+    reload_w<NB>(Ly, next, chain, wave, lane, s + 6, y0, y1);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
   }
   if (s < ks) mfma_pair<NB>(x0, x1, ax0, ax1, acc);  // ks = 4t + 2: the last pair
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(kThreads) k_bake(BakeArgs a) {
-  __shared__ __attribute__((aligned(16))) _Float16 act[kRows * kActStride];
-  __shared__ __attribute__((aligned(16))) _Float16 feat[kRows * kFeatStride];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * kRows;
+template <int NB>
+__device__ __forceinline__ void zero_acc(f32x16 (&acc)[4][kMaxBlk]) {
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][j][r] = 0.0f;
+}
 
-  // Fourier features: two threads per row, 32 columns each; the argument
-  // 2^j x is exact, sin(pi .) and cos(pi .) in FP64, rounded to binary16.
-  {
-    const int r = tid >> 1, c0 = (tid & 1) * 32;
-    int64_t q = row0 + r;
-    if (q >= a.npoints) q = a.npoints - 1;  // rows past the end repeat the last point
-    double x[3];
-    point_of<MODE>(a, q, x);
-    const int nf = 6 * a.freqs;
-    for (int cc = 0; cc < 32; ++cc) {
-      const int c = c0 + cc;
-      float v = 0.0f;
-      if (c < nf) {
-        const int j = c / 6, rem = c - 6 * j, ax = rem % 3;
-        const double arg = ldexp(x[ax], j);
-        v = (float)(rem < 3 ? sinpi(arg) : cospi(arg));
-      }
-      feat[r * kFeatStride + c] = (_Float16)v;
-    }
-  }
-  __syncthreads();
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 
+// The hidden layers for a wave owning NB column blocks of each (NB = 0: the
+// wave only joins the barriers). After a layer: bias + ReLU, binary16, into
+// the activation rows. Accumulator element r of lane l (transposed product)
+// is output column 8(r/4) + 4(l/32) + r%4 of the block, row l%32 of the row
+// block.
+template <int NB>
+__device__ void hidden_layers(const BakeArgs &a, _Float16 *act, const _Float16 *feat,
+                              const float *sbias, int wave, int lane) {
   const int mrow = lane & 31;
-  for (int li = 0; li <= a.nlayers; ++li) {
+  half8 x0[NB > 0 ? NB : 1], x1[NB > 0 ? NB : 1], y0[NB > 0 ? NB : 1], y1[NB > 0 ? NB : 1];
+  if constexpr (NB > 0) {
+    const BakeLayer L0 = a.L[0];
+    load_w<NB>(L0, wave, lane, 0, x0, x1);
+    load_w<NB>(L0, wave, lane, min(2, L0.ks_h + L0.ks_f - 2), y0, y1);
+  }
+  for (int li = 0; li < a.nlayers; ++li) {
     const BakeLayer Ly = a.L[li];
-    f32x16 acc[4][kMaxBlk];
+    if constexpr (NB > 0) {
+      f32x16 acc[4][kMaxBlk];
+      zero_acc<NB>(acc);
+      const bool more = li + 1 < a.nlayers;
+      const BakeLayer Ln = a.L[more ? li + 1 : li];
+      const bool chain = more && (Ly.ks_h + Ly.ks_f) % 4 == 0;
+      layer_gemm<NB>(Ly, Ln, chain, act, feat, wave, lane, x0, x1, y0, y1, acc);
+      if (more && !chain) {
+        load_w<NB>(Ln, wave, lane, 0, x0, x1);
+        load_w<NB>(Ln, wave, lane, min(2, Ln.ks_h + Ln.ks_f - 2), y0, y1);
+      }
+      __syncthreads();  // every wave has read this layer's input
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-      for (int j = 0; j < kMaxBlk; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[mb][j][r] = 0.0f;
-    // blocks of this wave: w, w+4, w+8 below nblk (wave-uniform)
-    const int nmine = Ly.nblk > wave ? (Ly.nblk - wave + kWaves - 1) / kWaves : 0;
-    if (nmine >= 3)
-      layer_gemm<3>(Ly, act, feat, wave, lane, acc);
-    else if (nmine == 2)
-      layer_gemm<2>(Ly, act, feat, wave, lane, acc);
-    else if (nmine == 1)
-      layer_gemm<1>(Ly, act, feat, wave, lane, acc);
-    __syncthreads();  // every wave has read this layer's input
-    // accumulator element r of lane l (transposed product): output column
-    // 8(r/4) + 4(l/32) + r%4 of the block, row l%32 of the row block
-    if (li < a.nlayers) {
-#pragma unroll
-      for (int j = 0; j < kMaxBlk; ++j) {
+      for (int j = 0; j < NB; ++j) {
         const int nb = wave + kWaves * j;
-        if (nb >= Ly.nblk) continue;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           const int n = 32 * nb + 8 * g + 4 * (lane >> 5);
-          const float4 bias = *reinterpret_cast<const float4 *>(Ly.b + n);
+          const float4 bias = *reinterpret_cast<const float4 *>(sbias + Ly.boff + n);
 #pragma unroll
           for (int mb = 0; mb < 4; ++mb) {
-            const int m = 32 * mb + mrow;
-            typedef _Float16 half4 __attribute__((ext_vector_type(4)));
             half4 v;
             v[0] = (_Float16)fmaxf(acc[mb][j][4 * g + 0] + bias.x, 0.0f);
             v[1] = (_Float16)fmaxf(acc[mb][j][4 * g + 1] + bias.y, 0.0f);
             v[2] = (_Float16)fmaxf(acc[mb][j][4 * g + 2] + bias.z, 0.0f);
             v[3] = (_Float16)fmaxf(acc[mb][j][4 * g + 3] + bias.w, 0.0f);
-            *reinterpret_cast<half4 *>(act + m * kActStride + n) = v;
+            *reinterpret_cast<half4 *>(act + (32 * mb + mrow) * kActStride + n) = v;
           }
         }
       }
-      __syncthreads();
     } else {
-      float *raw = reinterpret_cast<float *>(act);
-#pragma unroll
-      for (int j = 0; j < kMaxBlk; ++j) {
-        const int nb = wave + kWaves * j;
-        if (nb >= Ly.nblk) continue;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int n = 32 * nb + 8 * g + 4 * (lane >> 5);
-          const float4 bias = *reinterpret_cast<const float4 *>(Ly.b + n);
-#pragma unroll
-          for (int mb = 0; mb < 4; ++mb) {
-            const int m = 32 * mb + mrow;
-            float4 v;
-            v.x = acc[mb][j][4 * g + 0] + bias.x;
-            v.y = acc[mb][j][4 * g + 1] + bias.y;
-            v.z = acc[mb][j][4 * g + 2] + bias.z;
-            v.w = acc[mb][j][4 * g + 3] + bias.w;
-            *reinterpret_cast<float4 *>(raw + m * kRawStride + n) = v;
-          }
-        }
-      }
       __syncthreads();
-      const int D = a.D;
-      if (MODE == 0) {
-        const int nout = 1 + 3 * D;
-        for (int e = tid; e < kRows * nout; e += kThreads) {
-          const int r = e / nout, c = e - r * nout;
-          const int64_t q = row0 + r;
-          if (q >= a.npoints) continue;
-          const float v = raw[r * kRawStride + c];
-          if (c == 0)
-            a.out0[q] = fmaxf(v, 0.0f);
-          else
-            a.out1[q * (3 * D) + (c - 1)] = 1.0f / (1.0f + expf(-v));
-        }
-      } else if (tid < kRows) {
-        const int64_t q = row0 + tid;
-        if (q < a.npoints) {
-          const float *o = raw + tid * kRawStride;
-          float mx = o[0];
-          for (int d = 1; d < D; ++d) mx = fmaxf(mx, o[d]);
-          float sum = 0.0f;
-          for (int d = 0; d < D; ++d) sum += expf(o[d] - mx);
-          const float inv = 1.0f / sum;
-          for (int d = 0; d < D; ++d) a.out0[q * D + d] = expf(o[d] - mx) * inv;
+    }
+    __syncthreads();
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_bake(BakeArgs a) {
+  __shared__ __attribute__((aligned(16))) _Float16 act[kRows * kActStride];
+  __shared__ __attribute__((aligned(16))) _Float16 feat[kRows * kFeatStride];
+  __shared__ __attribute__((aligned(16))) float sbias[kMaxBias];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * kRows;
+
+  if (tid < kRows) {
+    // Fourier features of one row: sin and cos of pi x in FP64, then of
+    // 2^j pi x by the double-angle identities sin 2t = 2 sin t cos t,
+    // cos 2t = 1 - 2 sin^2 t (FP64: ten doublings keep the error near
+    // 1e-13), rounded to binary16.
+    int64_t q = row0 + tid;
+    if (q >= a.npoints) q = a.npoints - 1;  // rows past the end repeat the last point
+    double x[3], sn[3], cs[3];
+    point_of<MODE>(a, q, x);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      sn[ax] = sinpi(x[ax]);
+      cs[ax] = cospi(x[ax]);
+    }
+    _Float16 f[kFeat];
+#pragma unroll
+    for (int c = 0; c < kFeat; ++c) f[c] = (_Float16)0.0f;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+      if (j < a.freqs) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          f[6 * j + ax] = (_Float16)(float)sn[ax];
+          f[6 * j + 3 + ax] = (_Float16)(float)cs[ax];
+          const double s2 = 2.0 * sn[ax] * cs[ax];
+          const double c2 = 1.0 - 2.0 * sn[ax] * sn[ax];
+          sn[ax] = s2;
+          cs[ax] = c2;
         }
       }
+    }
+#pragma unroll
+    for (int c = 0; c < kFeat; c += 8) {
+      half8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = f[c + e];
+      *reinterpret_cast<half8 *>(feat + tid * kFeatStride + c) = v;
+    }
+  } else {
+    for (int i = tid - kRows; i < a.nbias; i += kThreads - kRows) sbias[i] = a.bias[i];
+  }
+  __syncthreads();
+
+  // hidden layers: the wave's blocks w, w+4, w+8 below nblk (wave-uniform)
+  const int nblk_h = a.L[0].nblk;
+  const int nmine = nblk_h > wave ? (nblk_h - wave + kWaves - 1) / kWaves : 0;
+  if (nmine >= 3)
+    hidden_layers<3>(a, act, feat, sbias, wave, lane);
+  else if (nmine == 2)
+    hidden_layers<2>(a, act, feat, sbias, wave, lane);
+  else if (nmine == 1)
+    hidden_layers<1>(a, act, feat, sbias, wave, lane);
+  else
+    hidden_layers<0>(a, act, feat, sbias, wave, lane);
+
+  // output layer (at most two blocks: waves 0 and 1), raw FP32 values to LDS
+  const BakeLayer Lo = a.L[a.nlayers];
+  const int mrow = lane & 31;
+  f32x16 acc[4][kMaxBlk];
+  if (wave < Lo.nblk) {
+    half8 x0[1], x1[1], y0[1], y1[1];
+    load_w<1>(Lo, wave, lane, 0, x0, x1);
+    load_w<1>(Lo, wave, lane, min(2, Lo.ks_h + Lo.ks_f - 2), y0, y1);
+    zero_acc<1>(acc);
+    layer_gemm<1>(Lo, Lo, false, act, feat, wave, lane, x0, x1, y0, y1, acc);
+  }
+  __syncthreads();  // the raw values overwrite the activations
+  float *raw = reinterpret_cast<float *>(act);
+  if (wave < Lo.nblk) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int n = 32 * wave + 8 * g + 4 * (lane >> 5);
+      const float4 bias = *reinterpret_cast<const float4 *>(sbias + Lo.boff + n);
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        float4 v;
+        v.x = acc[mb][0][4 * g + 0] + bias.x;
+        v.y = acc[mb][0][4 * g + 1] + bias.y;
+        v.z = acc[mb][0][4 * g + 2] + bias.z;
+        v.w = acc[mb][0][4 * g + 3] + bias.w;
+        *reinterpret_cast<float4 *>(raw + (32 * mb + mrow) * kRawStride + n) = v;
+      }
+    }
+  }
+  __syncthreads();
+  const int D = a.D;
+  if (MODE == 0) {
+    const int nout = 1 + 3 * D;
+    for (int e = tid; e < kRows * nout; e += kThreads) {
+      const int r = e / nout, c = e - r * nout;
+      const int64_t q = row0 + r;
+      if (q >= a.npoints) continue;
+      const float v = raw[r * kRawStride + c];
+      if (c == 0)
+        a.out0[q] = fmaxf(v, 0.0f);
+      else
+        a.out1[q * (3 * D) + (c - 1)] = 1.0f / (1.0f + expf(-v));
+    }
+  } else if (tid < kRows) {
+    const int64_t q = row0 + tid;
+    if (q < a.npoints) {
+      const float *o = raw + tid * kRawStride;
+      float mx = o[0];
+      for (int d = 1; d < D; ++d) mx = fmaxf(mx, o[d]);
+      float sum = 0.0f;
+      for (int d = 0; d < D; ++d) sum += expf(o[d] - mx);
+      const float inv = 1.0f / sum;
+      for (int d = 0; d < D; ++d) a.out0[q * D + d] = expf(o[d] - mx) * inv;
     }
   }
 }
@@ -335,6 +417,8 @@ struct fastnerf_mlp_s {
   int device = 0;
   uint8_t *buf = nullptr;
   fnr::BakeLayer net[2][fnr::kMaxLayers + 1];
+  const float *bias[2] = {nullptr, nullptr};  // each network's biases (device)
+  int nbias[2] = {0, 0};
   hipEvent_t last_use = nullptr;
 };
 
@@ -353,14 +437,13 @@ extern "C" fastnerf_status fastnerf_mlp_create(const fastnerf_mlp_desc *desc,
   if (is_device_ptr(pos_params) || is_device_ptr(dir_params))
     return fail(FASTNERF_EINVAL, "network parameters must be host arrays");
   const float *params[2] = {pos_params, dir_params};
-  // pack every layer: B fragments (binary16) then the padded bias, each
-  // 256-byte aligned, both networks in one device buffer
+  // pack every layer's weight fragments (binary16, 256-byte aligned), then
+  // each network's biases (every layer padded to nblk * 32 floats), all in
+  // one device buffer
   std::vector<uint8_t> host;
-  struct Off {
-    size_t w, b;
-  };
-  std::vector<Off> offs[2];
-  int shape_ks[2][kMaxLayers + 1][3];
+  std::vector<size_t> woff[2];
+  std::vector<float> biases[2];
+  int shape_ks[2][kMaxLayers + 1][4];
   for (int which = 0; which < 2; ++which) {
     const NetShape n = net_shape(desc, which);
     const int64_t count = param_count(n);
@@ -379,12 +462,10 @@ extern "C" fastnerf_status fastnerf_mlp_create(const fastnerf_mlp_desc *desc,
       shape_ks[which][i][0] = ks_h;
       shape_ks[which][i][1] = ks_f;
       shape_ks[which][i][2] = nblk;
-      Off o;
-      o.w = (host.size() + 255) & ~(size_t)255;
-      const size_t wbytes = (size_t)ks * nblk * 64 * 16;
-      o.b = (o.w + wbytes + 255) & ~(size_t)255;
-      host.resize(o.b + (size_t)nblk * 32 * 4, 0);
-      _Float16 *wf = reinterpret_cast<_Float16 *>(host.data() + o.w);
+      shape_ks[which][i][3] = (int)biases[which].size();
+      const size_t w0 = (host.size() + 255) & ~(size_t)255;
+      host.resize(w0 + (size_t)ks * nblk * 64 * 16, 0);
+      _Float16 *wf = reinterpret_cast<_Float16 *>(host.data() + w0);
       for (int s = 0; s < ks; ++s)
         for (int nb = 0; nb < nblk; ++nb)
           for (int l = 0; l < 64; ++l)
@@ -401,9 +482,19 @@ extern "C" fastnerf_status fastnerf_mlp_create(const fastnerf_mlp_desc *desc,
               const float v = (row >= 0 && col < fo) ? W[(size_t)row * fo + col] : 0.0f;
               wf[(((size_t)s * nblk + nb) * 64 + l) * 8 + e] = (_Float16)v;
             }
-      memcpy(host.data() + o.b, b, (size_t)fo * 4);
-      offs[which].push_back(o);
+      woff[which].push_back(w0);
+      const size_t b0 = biases[which].size();
+      biases[which].resize(b0 + (size_t)nblk * 32, 0.0f);
+      memcpy(biases[which].data() + b0, b, (size_t)fo * 4);
     }
+  }
+  size_t boff[2];
+  for (int which = 0; which < 2; ++which)
+    if (biases[which].size() > (size_t)kMaxBias) return fail(FASTNERF_EINVAL, "too many biases");
+  for (int which = 0; which < 2; ++which) {
+    boff[which] = (host.size() + 255) & ~(size_t)255;
+    host.resize(boff[which] + biases[which].size() * 4, 0);
+    memcpy(host.data() + boff[which], biases[which].data(), biases[which].size() * 4);
   }
   fastnerf_mlp_s *m = new (std::nothrow) fastnerf_mlp_s();
   if (!m) return fail(FASTNERF_ENOMEM, "host allocation");
@@ -417,15 +508,18 @@ extern "C" fastnerf_status fastnerf_mlp_create(const fastnerf_mlp_desc *desc,
     fastnerf_mlp_destroy(m);
     return st;
   }
-  for (int which = 0; which < 2; ++which)
-    for (size_t i = 0; i < offs[which].size(); ++i) {
+  for (int which = 0; which < 2; ++which) {
+    m->bias[which] = reinterpret_cast<const float *>(m->buf + boff[which]);
+    m->nbias[which] = (int)biases[which].size();
+    for (size_t i = 0; i < woff[which].size(); ++i) {
       BakeLayer &L = m->net[which][i];
-      L.w = reinterpret_cast<const half8 *>(m->buf + offs[which][i].w);
-      L.b = reinterpret_cast<const float *>(m->buf + offs[which][i].b);
+      L.w = reinterpret_cast<const half8 *>(m->buf + woff[which][i]);
       L.ks_h = shape_ks[which][i][0];
       L.ks_f = shape_ks[which][i][1];
       L.nblk = shape_ks[which][i][2];
+      L.boff = shape_ks[which][i][3];
     }
+  }
   *out = m;
   return FASTNERF_OK;
 }
@@ -434,6 +528,8 @@ static fastnerf_status launch_bake(fastnerf_mlp m, int which, BakeArgs &a, hipSt
   const fastnerf_mlp_desc &d = m->desc;
   const NetShape n = net_shape(&d, which);
   for (int i = 0; i <= n.layers; ++i) a.L[i] = m->net[which][i];
+  a.bias = m->bias[which];
+  a.nbias = m->nbias[which];
   a.nlayers = n.layers;
   a.freqs = n.freqs;
   a.D = d.D;
