@@ -150,25 +150,30 @@ __device__ __forceinline__ void reload_w(const BakeLayer &Ly, const BakeLayer &n
 // of weight and activation registers alternate (steps s, s+1 and s+2, s+3):
 // a set is reloaded, two steps ahead, as soon as its products are issued, so
 // a weight load has the other set's products to arrive. On entry the sets
-// hold steps 0-3; with chain (next layer: same block count; ks a multiple of 4)
-// they hold the next layer's steps 0-3 on return, so its weights arrive
-// while this layer is written back.
-template <int NB>
+// hold steps 0-3; with chain (next layer: same block count; ks a multiple of
+// 4) they hold the next layer's steps 0-3 on return, so its weights arrive
+// while this layer is written back. KSH/KSF > 0 fix the k-steps at compile
+// time and unroll the loop completely: straight-line code lets the compiler
+// wait for exactly the set in use (in a loop it waited for every load at the
+// top of each iteration); KSH < 0 is the general loop.
+template <int NB, int KSH, int KSF>
 __device__ __forceinline__ void layer_gemm(const BakeLayer &Ly, const BakeLayer &next,
-                                           bool chain, const _Float16 *act, const _Float16 *feat, int wave,
-                                           int lane, half8 (&x0)[NB], half8 (&x1)[NB],
-                                           half8 (&y0)[NB], half8 (&y1)[NB],
-                                           f32x16 (&acc)[4][kMaxBlk]) {
+                                           bool chain, const _Float16 *act,
+                                           const _Float16 *feat, int wave, int lane,
+                                           half8 (&x0)[NB], half8 (&x1)[NB], half8 (&y0)[NB],
+                                           half8 (&y1)[NB], f32x16 (&acc)[4][kMaxBlk]) {
   const int mrow = lane & 31, kq = (lane >> 5) * 8;
-  const int ks = Ly.ks_h + Ly.ks_f;  // even: hidden widths are multiples of 32
+  constexpr bool kFixed = KSH >= 0;
+  const int ks = kFixed ? KSH + KSF : Ly.ks_h + Ly.ks_f;  // even: widths are multiples of 32
   const int last = ks - 2;
   half8 ax0[4], ax1[4], ay0[4], ay1[4];
   load_act(Ly, act, feat, 0, mrow, kq, ax0, ax1);
   // both halves in every iteration, so that loads complete in one order on
   // every path (the wait before a set's products then spares the other set)
   int s = 0;
-  for (; s + 4 <= ks; s += 4) {
+  auto body = [&](int s) {
     load_act(Ly, act, feat, min(s + 2, last), mrow, kq, ay0, ay1);
+    __builtin_amdgcn_sched_barrier(0);  // activation reads go out first
     mfma_pair<NB>(x0, x1, ax0, ax1, acc);
     reload_w<NB>(Ly, next, chain, wave, lane, s + 4, x0, x1);
     // neither the compiler nor the scheduler moves anything across: the
@@ -176,12 +181,44 @@ __device__ __forceinline__ void layer_gemm(const BakeLayer &Ly, const BakeLayer 
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     load_act(Ly, act, feat, min(s + 4, last), mrow, kq, ax0, ax1);
+    __builtin_amdgcn_sched_barrier(0);
     mfma_pair<NB>(y0, y1, ay0, ay1, acc);
     reload_w<NB>(Ly, next, chain, wave, lane, s + 6, y0, y1);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
+  };
+  if constexpr (kFixed) {
+#pragma unroll
+    for (int t = 0; t + 4 <= KSH + KSF; t += 4) body(t);
+    s = (KSH + KSF) / 4 * 4;
+  } else {
+    for (; s + 4 <= ks; s += 4) body(s);
   }
   if (s < ks) mfma_pair<NB>(x0, x1, ax0, ax1, acc);  // ks = 4t + 2: the last pair
+}
+
+// layer_gemm with the k-steps of the common widths fixed at compile time.
+template <int NB>
+__device__ __forceinline__ void layer_gemm_any(const BakeLayer &Ly, const BakeLayer &next,
+                                               bool chain, const _Float16 *act,
+                                               const _Float16 *feat, int wave, int lane,
+                                               half8 (&x0)[NB], half8 (&x1)[NB],
+                                               half8 (&y0)[NB], half8 (&y1)[NB],
+                                               f32x16 (&acc)[4][kMaxBlk]) {
+#define FNR_GEMM(H, F)                                                                   \
+  if (Ly.ks_h == (H) && Ly.ks_f == (F)) {                                                \
+    layer_gemm<NB, H, F>(Ly, next, chain, act, feat, wave, lane, x0, x1, y0, y1, acc);   \
+    return;                                                                              \
+  }
+  FNR_GEMM(0, 4)
+  FNR_GEMM(24, 0)
+  FNR_GEMM(24, 4)
+  FNR_GEMM(16, 0)
+  FNR_GEMM(16, 4)
+  FNR_GEMM(8, 0)
+  FNR_GEMM(8, 4)
+#undef FNR_GEMM
+  layer_gemm<NB, -1, -1>(Ly, next, chain, act, feat, wave, lane, x0, x1, y0, y1, acc);
 }
 
 template <int NB>
@@ -219,7 +256,7 @@ __device__ void hidden_layers(const BakeArgs &a, _Float16 *act, const _Float16 *
       const bool more = li + 1 < a.nlayers;
       const BakeLayer Ln = a.L[more ? li + 1 : li];
       const bool chain = more && (Ly.ks_h + Ly.ks_f) % 4 == 0;
-      layer_gemm<NB>(Ly, Ln, chain, act, feat, wave, lane, x0, x1, y0, y1, acc);
+      layer_gemm_any<NB>(Ly, Ln, chain, act, feat, wave, lane, x0, x1, y0, y1, acc);
       if (more && !chain) {
         load_w<NB>(Ln, wave, lane, 0, x0, x1);
         load_w<NB>(Ln, wave, lane, min(2, Ln.ks_h + Ln.ks_f - 2), y0, y1);
@@ -322,7 +359,7 @@ __global__ void __launch_bounds__(kThreads) k_bake(BakeArgs a) {
     load_w<1>(Lo, wave, lane, 0, x0, x1);
     load_w<1>(Lo, wave, lane, min(2, Lo.ks_h + Lo.ks_f - 2), y0, y1);
     zero_acc<1>(acc);
-    layer_gemm<1>(Lo, Lo, false, act, feat, wave, lane, x0, x1, y0, y1, acc);
+    layer_gemm_any<1>(Lo, Lo, false, act, feat, wave, lane, x0, x1, y0, y1, acc);
   }
   __syncthreads();  // the raw values overwrite the activations
   float *raw = reinterpret_cast<float *>(act);
