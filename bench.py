@@ -35,6 +35,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_10380_amd", "csrc", f)
                   for f in ("fastnerf_kernels.hip", "fastnerf_device.h")]
 
 
+def bake_digest():
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_2103_10380_amd", "csrc",
+                                         "fastnerf_bake.hip"), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def kernel_digest():
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -290,6 +296,100 @@ def batched_uneven(fn, reps=10):
             "mrays_per_s": round(rays / (float(np.mean(ms)) / 1e3) / 1e6, 1)}
 
 
+MFMA_F16_PEAK_TFLOPS = 2500.0  # MI355X dense binary16 matrix peak
+
+
+def bake_measure(fn, k=768, l=384, slab=64, sample=3000, cpu_points=1 << 18, with_cpu=True):
+    """Cache bake of the paper's networks (Sec. 4: 8 x 384 position MLP, skip
+    input at layer 5, L = 10; 4 x 128 direction MLP, L = 4; D = 8; random
+    binary16 weights, seed 7): the whole k^3 position grid in launches of
+    `slab` layers and the l x l direction grid, HIP events per launch.
+    Sampled parity against the oracle and the oracle's own rate on a bounded
+    sample belong to the CPU leg."""
+    import torch
+    import synth
+    spec = synth.MlpSpec()
+    w = synth.mlp_weights(spec)
+    net = fn.Mlp(spec, w)
+    pos_shapes, dir_shapes = synth.mlp_shapes(spec)
+    flop_pt = 2 * sum(a * b for a, b in pos_shapes)
+    box = ((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+    sig = torch.empty((slab, k, k), dtype=torch.float32, device="cuda")
+    u = torch.empty((slab, k, k, spec.D, 3), dtype=torch.float32, device="cuda")
+    net.bake_position(k, *box, 0, slab, sig, u)  # warm-up
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for z0 in range(0, k, slab):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        net.bake_position(k, *box, z0, min(slab, k - z0), sig, u)
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([a.elapsed_time(b) for a, b in evs])
+    pts = k ** 3
+    launch_pts = slab * k * k
+    achieved = flop_pt * launch_pts / (ms.mean() / 1e3) / 1e12
+    beta = net.bake_direction(l)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    net.bake_direction(l, beta)
+    b.record()
+    torch.cuda.synchronize()
+    out = {
+        "workload": (f"F_pos (8 x 384, skip at layer 5, L=10, D=8) at the {k}^3 voxel centres "
+                     f"in {len(evs)} launches of {slab} layers; F_dir (4 x 128, L=4) on the "
+                     f"{l}^2 direction grid; random binary16 weights (seed 7)"),
+        "position_mpoints_per_s": round(pts / wall / 1e6, 1),
+        "position_grid_s": round(wall, 3),
+        "launch_ms_mean": round(float(ms.mean()), 3),
+        "direction_grid_ms": round(a.elapsed_time(b), 4),
+        "flop_per_point": flop_pt,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 1),
+                     "peak": MFMA_F16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / MFMA_F16_PEAK_TFLOPS, 4),
+                     "kernel": "k_bake<position>, binary16 products, FP32 accumulation",
+                     "algorithmic_flop_per_launch": flop_pt * launch_pts},
+        "uncached_frame_ms_est": round(800 * 800 * 192 / (pts / wall) * 1e3, 1),
+    }
+    if with_cpu:
+        from oracle import mlp as omlp
+        rng = np.random.default_rng(5)
+        z0 = k - slab  # the last launch's layers are still in sig / u
+        idx = np.stack([rng.integers(0, k, sample), rng.integers(0, k, sample),
+                        rng.integers(z0, k, sample)], axis=1)
+        rows = (idx[:, 2] - z0) * k * k + idx[:, 1] * k + idx[:, 0]
+        s_ref, u_ref = omlp.bake_position(w, spec, k, *box, idx)
+        s_g = sig.reshape(-1)[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+        u_g = u.reshape(-1, spec.D, 3)[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+        cells = omlp.grid_indices(l)[rng.choice(l * l, sample, replace=False)]
+        b_ref = omlp.bake_direction(w, spec, l, cells)
+        b_g = beta.reshape(-1, spec.D).cpu().numpy()[cells[:, 0] * l + cells[:, 1]]
+        out["parity"] = {"points": sample, "sigma_max_abs_err": float(np.abs(s_g - s_ref).max()),
+                         "u_max_abs_err": float(np.abs(u_g - u_ref).max()),
+                         "beta_max_abs_err": float(np.abs(b_g - b_ref).max()),
+                         "reference": "FP64 oracle (oracle/mlp.py)"}
+        t_cpu = 0.0
+        for c0 in range(0, cpu_points, 16384):  # bounded memory per call
+            cidx = np.stack([rng.integers(0, k, 16384) for _ in range(3)], axis=1)
+            t1 = time.perf_counter()
+            omlp.bake_position(w, spec, k, *box, cidx)
+            t_cpu += time.perf_counter() - t1
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            cores = None
+        out["cpu_baseline"] = {"value": round(cpu_points / t_cpu / 1e6, 5), "unit": "Mpoints/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"{cpu_points} voxel centres, FP64 numpy, {t_cpu:.2f} s"}
+    net.destroy()
+    return out
+
+
 def voxel_sweep(fn, main=None, ks=(256, 384, 512, 768), nviews=8, reps=3, pix=200):
     """The per-voxel integration (N = 0: every voxel a ray crosses) against N=192
     samples in the box, on the paper-scale generator at several k (seed 1,
@@ -503,6 +603,8 @@ def main():
                     help="only the serving workload: four resident scenes, Poisson arrivals "
                          "at 50/100/200/400/1600/6400 requests/s (one JSON line)")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--bake", action="store_true",
+                    help="only the cache bake of the paper's networks (one JSON line)")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-view latency launches (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
@@ -548,6 +650,14 @@ def main():
                                    "poses, N=192 in the box, eps=1e-4, seed 3",
                        "warmup_requests": 100, "requests_per_rate": args.serve_requests},
             "rates": rows, "kernel_digest": kernel_digest()}), flush=True)
+        return
+
+    if args.bake:
+        r = bake_measure(fn, with_cpu=not args.no_cpu)
+        print(json.dumps({"metric": "cache bake throughput (position network)",
+                          "value": r["position_mpoints_per_s"], "unit": "Mpoints/s",
+                          "n_gpus": 1, "dtype": "f16", "data": "synthetic", **r,
+                          "bake_digest": bake_digest()}), flush=True)
         return
 
     N, eps = 192, 1e-4
@@ -705,6 +815,8 @@ def main():
         log(f"batched uneven: {line['batched_uneven']}")
         line["precision_sweep"] = precision_sweep(fn)
         log(f"precision sweep: {line['precision_sweep']}")
+        line["bake"] = bake_measure(fn, with_cpu=not args.no_cpu)
+        log(f"bake: {line['bake']}")
     line["kernel_digest"] = kernel_digest()
     print(json.dumps(line), flush=True)
 
