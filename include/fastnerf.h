@@ -261,6 +261,31 @@ fastnerf_status fastnerf_bake_direction(fastnerf_mlp mlp, int32_t l, float *beta
 /* Waits for the network's outstanding bakes, then frees it. */
 fastnerf_status fastnerf_mlp_destroy(fastnerf_mlp mlp);
 
+/* ------------------------------------------------ direction filtering and LOD */
+
+/* Smooths a direction-cache table beta[l][l][D] (theta row, phi column) with
+ * a Gaussian of standard deviation `sigma` cells on each axis (Sec. 4: the
+ * direction cache can be processed with a Gaussian or other kernel to smooth
+ * directional effects): out[j][m] = sum_{a,b} g(a) g(b) in[clamp(j+a)][(m+b)
+ * mod l] with g(t) = exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma),
+ * normalised to sum 1 -- periodic in phi, the edge rows repeated in theta
+ * (the lookup clamps theta the same way). Convex combinations stay convex, so
+ * rows summing to 1 still do. sigma in [0, 10]; 0 copies. Device arrays;
+ * beta_out must not overlap beta_in. Enqueued on `stream`. */
+fastnerf_status fastnerf_filter_direction(const float *beta_in, int32_t l, int32_t D, float sigma,
+                                          float *beta_out, hipStream_t stream);
+
+/* Level-of-detail choice among caches of one scene at several resolutions
+ * ks[0..n-1] over the same box (Sec. 5: smaller caches trade detail for speed
+ * and memory like levels of detail): the coarsest level whose voxel edge
+ * (longest box side / k) is at most `ratio` times the footprint of one pixel
+ * at the box centre (distance from the camera to the centre / focal length
+ * K[0]); the finest level if none is. Host only. Returns the index, or -1 for
+ * bad arguments (n < 1, k < 1, ratio <= 0, K[0] <= 0, non-finite input). */
+int32_t fastnerf_lod_select(const int32_t *ks, int32_t n, const float bbox_min[3],
+                            const float bbox_max[3], const float K[9], const float c2w[12],
+                            float ratio);
+
 /* Thread-local message for the last non-OK status of this thread. */
 const char *fastnerf_last_error(void);
 

@@ -83,6 +83,8 @@ SYMBOLS = {
     "fastnerf_bake_position": (_i32, [_vp, _i32, _pf, _pf, _i32, _i32, _vp, _vp, _vp]),
     "fastnerf_bake_direction": (_i32, [_vp, _i32, _vp, _vp]),
     "fastnerf_mlp_destroy": (_i32, [_vp]),
+    "fastnerf_filter_direction": (_i32, [_vp, _i32, _i32, _f32, _vp, _vp]),
+    "fastnerf_lod_select": (_i32, [ctypes.POINTER(_i32), _i32, _pf, _pf, _pf, _pf, _f32]),
     "fastnerf_last_error": (ctypes.c_char_p, []),
 }
 
@@ -429,3 +431,24 @@ class Mlp:
                 self.handle = None
         except Exception:
             pass
+
+
+def filter_direction(beta, sigma, out=None, stream=None):
+    """Gaussian-smoothed copy of a device direction table beta [l, l, D]."""
+    import torch
+    l, D = beta.shape[0], beta.shape[-1]
+    if out is None:
+        out = torch.empty_like(beta)
+    check(lib().fastnerf_filter_direction(_ptr(beta), l, D, float(sigma), _ptr(out),
+                                          _stream(stream)))
+    return out
+
+
+def lod_select(ks, bbox_min, bbox_max, K, c2w, ratio=1.0):
+    """Index of the level of detail among caches of resolutions ks (-1: bad arguments)."""
+    arr = (ctypes.c_int32 * len(ks))(*[int(k) for k in ks])
+    lo, lp = _arr9(bbox_min, 3)
+    hi, hp = _arr9(bbox_max, 3)
+    k_, kp = _arr9(K, 9)
+    c_, cp = _arr9(c2w, 12)
+    return lib().fastnerf_lod_select(arr, len(ks), lp, hp, kp, cp, float(ratio))

@@ -10,7 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfastnerf.so")
-SOURCES = ["fastnerf_kernels.hip", "fastnerf_api.hip", "fastnerf_serve.hip", "fastnerf_bake.hip"]
+SOURCES = ["fastnerf_kernels.hip", "fastnerf_api.hip", "fastnerf_serve.hip", "fastnerf_bake.hip",
+           "fastnerf_direction.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -105,3 +105,30 @@ def test_mlp_descriptors_checked_without_device(L):
                                      ctypes.byref(h)) == -1, field
     assert L.fastnerf_mlp_destroy(None) == -1
     assert L.fastnerf_bake_direction(None, 8, None, None) == -1
+
+
+def test_lod_select_matches_oracle(L):
+    """Host-only: the library's level-of-detail choice equals the oracle's on
+    random cameras, boxes and level sets."""
+    import numpy as np
+    import synth
+    from oracle import direction as odir
+    from paper_2103_10380_amd import _lib
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        n = int(rng.integers(1, 6))
+        ks = list(rng.choice([64, 128, 256, 384, 512, 768, 1024], n, replace=False))
+        lo = rng.uniform(-2, 0, 3)
+        hi = lo + rng.uniform(0.5, 3, 3)
+        v = synth.orbit_view(float(rng.uniform(2, 30)), float(rng.uniform(0, 6)),
+                             float(rng.uniform(-1, 1)), 64, 64, 0.1, 50.0,
+                             f=float(rng.uniform(20, 2000)))
+        ratio = float(rng.uniform(0.1, 4))
+        assert _lib.lod_select(ks, lo, hi, v.K, v.c2w, ratio) == \
+            odir.lod_select(ks, lo, hi, v.K, v.c2w, ratio)
+    v = synth.orbit_view(3.0, 0.0, 0.0, 8, 8, 0.1, 5.0)
+    assert _lib.lod_select([], (-1,) * 3, (1,) * 3, v.K, v.c2w) == -1
+    assert _lib.lod_select([256, 0], (-1,) * 3, (1,) * 3, v.K, v.c2w) == -1
+    assert _lib.lod_select([256], (-1,) * 3, (1,) * 3, v.K, v.c2w, 0.0) == -1
+    assert _lib.lod_select([256], (1,) * 3, (1,) * 3, v.K, v.c2w) == -1
+    assert L.fastnerf_filter_direction(None, 8, 3, ctypes.c_float(1.0), None, None) == -1
