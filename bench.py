@@ -808,6 +808,14 @@ def main():
             line["serving_sample"] = r
             log(f"serving sample: p50 {r['latency_ms_p50']} ms p99 {r['latency_ms_p99']} ms")
         line["voxel_traversal"] = voxel_sweep(fn, (spec.k, caches.get("f32"), sparse, beta))
+        # level of detail: the level the library picks for the orbit's camera
+        # among the swept resolutions, and its cost from the sweep
+        ks = sorted(int(k) for k in line["voxel_traversal"])
+        pick = ks[fn.lod_select(ks, (-1.0,) * 3, (1.0,) * 3, views[0].K, views[0].c2w, 1.0)]
+        line["lod"] = {"levels": ks, "ratio": 1.0, "picked_k": pick,
+                       "n192_ms_per_view": line["voxel_traversal"][str(pick)]["n192"]["ms_per_view"],
+                       "rule": "coarsest k whose voxel edge <= ratio x pixel footprint at the "
+                               "box centre"}
         for c in caches.values():
             c.destroy()
         caches = {}
