@@ -8,7 +8,8 @@
 struct fastnerf_cache_s {
   fastnerf_cache_desc desc;
   int device = 0;
-  uint8_t *rec = nullptr;      // records, brick-linear, stride bytes each
+  uint8_t *rec = nullptr;      // records, brick-linear, stride bytes each (brick-sparse: the
+                               // all-zero brick, then the stored bricks in brick order)
   float *beta = nullptr;       // [l][l][D]
   uint32_t *occ = nullptr;     // occupancy bits
   uint8_t *dist = nullptr;     // per-brick Chebyshev distance to the nearest occupied brick
