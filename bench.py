@@ -601,7 +601,7 @@ def main():
                     help="print a summary of rocprofv3 CSV output directories and exit")
     ap.add_argument("--serving", action="store_true",
                     help="only the serving workload: four resident scenes, Poisson arrivals "
-                         "at 50/100/200/400/1600/6400 requests/s (one JSON line)")
+                         "at 50/100/200/400/1600/6400/12800 requests/s (one JSON line)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--bake", action="store_true",
                     help="only the cache bake of the paper's networks (one JSON line)")
@@ -636,7 +636,7 @@ def main():
         caches = serving_scenes(fn)
         log(f"serving scenes built in {time.perf_counter() - t0:.1f}s")
         rows = []
-        for lam in (50, 100, 200, 400, 1600, 6400):
+        for lam in (50, 100, 200, 400, 1600, 6400, 12800):
             r = serve_poisson(fn, caches, lam, args.serve_requests, 100)
             log(f"lambda {lam}: p50 {r['latency_ms_p50']} ms p99 {r['latency_ms_p99']} ms, "
                 f"{r['frames_per_s']} frames/s")

@@ -653,8 +653,13 @@ __global__ void __launch_bounds__(kBlock) k_render_vox(RenderArgs a) {
 // Serving step: tile ranges of many views over several resident caches of any
 // storage format, in one launch; the step's size is read from device memory so
 // the launch can be replayed from a captured graph.
+// Nearest lookups with up to 8 components are compiled for 3 waves per SIMD
+// (the four formats' code in one kernel would otherwise leave 2).
+constexpr int step_waves(int maxd, bool lin) { return maxd <= 8 && !lin ? 3 : 1; }
+
 template <int MAXD, bool LIN>
-__global__ void __launch_bounds__(kBlock) k_render_step(RenderArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves(MAXD, LIN))))
+k_render_step(RenderArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int total = __builtin_amdgcn_readfirstlane(a.dyn_total[0]);
   const int nviews = __builtin_amdgcn_readfirstlane(a.dyn_total[1]);

@@ -44,6 +44,8 @@ class GpuExecutor : public fs::Executor {
     max_views_ = max_views;
     arena_ = arena;
     HIP_CHECK(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k)
+      HIP_CHECK(hipEventCreateWithFlags(&done_[k], hipEventDisableTiming));
     std::vector<DevCache> dc;
     for (auto *c : scenes) dc.push_back(dev_cache(c));
     HIP_CHECK(hipMalloc(&caches_, sizeof(DevCache) * dc.size()));
@@ -58,6 +60,15 @@ class GpuExecutor : public fs::Executor {
   }
 
   fs::Status run(const fs::Step &step, uint64_t) override {
+    const fs::Status st = launch(step, 0);
+    return st == fs::kOk ? wait(0) : st;
+  }
+
+  // Enqueues the step's launches with the descriptor tables of slot `slot`
+  // (0 or 1: the scheduler alternates them and waits for a slot before it
+  // reuses it, so the pinned table of a step in flight is never rewritten).
+  fs::Status launch(const fs::Step &step, int slot) override {
+    slot &= 1;
     // one launch per (interpolation, component-count) class present
     std::map<int, std::vector<const fs::Segment *>> groups;
     for (const auto &sg : step.segs) {
@@ -67,8 +78,8 @@ class GpuExecutor : public fs::Executor {
     for (auto &kv : groups) {
       Group *g = nullptr;
       if (group(kv.first, &g) != FASTNERF_OK) return fs::kDevice;
-      StepHeader *hh = reinterpret_cast<StepHeader *>(g->h_table);
-      DevView *hv = reinterpret_cast<DevView *>(g->h_table + sizeof(StepHeader));
+      StepHeader *hh = reinterpret_cast<StepHeader *>(g->h_table[slot]);
+      DevView *hv = reinterpret_cast<DevView *>(g->h_table[slot] + sizeof(StepHeader));
       int tb = 0, n = 0;
       for (const fs::Segment *sg : kv.second) {
         const fs::Request *r = sg->req;
@@ -84,22 +95,28 @@ class GpuExecutor : public fs::Executor {
       }
       hh->total = tb;
       hh->nviews = n;
-      if (hipGraphLaunch(g->exec, stream_) != hipSuccess) return fs::kDevice;
+      if (hipGraphLaunch(g->exec[slot], stream_) != hipSuccess) return fs::kDevice;
       for (const fs::Segment *sg : kv.second)
         if (hipEventRecord(scenes_[sg->req->scene]->last_use, stream_) != hipSuccess)
           return fs::kDevice;
     }
-    // the pinned tables are rewritten next step: wait for this one
-    return hipStreamSynchronize(stream_) == hipSuccess ? fs::kOk : fs::kDevice;
+    return hipEventRecord(done_[slot], stream_) == hipSuccess ? fs::kOk : fs::kDevice;
+  }
+
+  fs::Status wait(int slot) override {
+    return hipEventSynchronize(done_[slot & 1]) == hipSuccess ? fs::kOk : fs::kDevice;
   }
 
  private:
+  // Per group: a pinned descriptor table and a captured graph (table copy,
+  // then the step kernel) for each of the two slots; the device table and the
+  // queue counters are shared, since the steps run in order on one stream.
   struct Group {
-    uint8_t *h_table = nullptr;  // pinned
+    uint8_t *h_table[2] = {nullptr, nullptr};  // pinned
     uint8_t *d_table = nullptr;
     unsigned *counter = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
   };
 
   // (interpolation, component-count class): the class fixes the record layout
@@ -114,8 +131,10 @@ class GpuExecutor : public fs::Executor {
       return FASTNERF_OK;
     }
     std::unique_ptr<Group> g(new Group());
-    HIP_CHECK(hipHostMalloc(&g->h_table, table_bytes_, hipHostMallocDefault));
-    memset(g->h_table, 0, table_bytes_);
+    for (int k = 0; k < 2; ++k) {
+      HIP_CHECK(hipHostMalloc(&g->h_table[k], table_bytes_, hipHostMallocDefault));
+      memset(g->h_table[k], 0, table_bytes_);
+    }
     HIP_CHECK(hipMalloc(&g->d_table, table_bytes_));
     HIP_CHECK(hipMalloc(&g->counter, kQueueCounters * sizeof(unsigned)));
     HIP_CHECK(hipMemset(g->counter, 0, kQueueCounters * sizeof(unsigned)));
@@ -129,14 +148,16 @@ class GpuExecutor : public fs::Executor {
     a.caches = caches_;
     a.counter = g->counter;
     a.nwaves = (unsigned)grid * (kBlock / kWave);
-    HIP_CHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipMemcpyAsync(g->d_table, g->h_table, table_bytes_, hipMemcpyHostToDevice,
-                                  stream_);
-    if (e == hipSuccess) e = launch_render_step(lin, D, a, grid, stream_);
-    hipError_t e2 = hipStreamEndCapture(stream_, &g->graph);
-    if (e != hipSuccess) return hip_fail(e, "step capture");
-    if (e2 != hipSuccess) return hip_fail(e2, "end capture");
-    HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    for (int k = 0; k < 2; ++k) {
+      HIP_CHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipMemcpyAsync(g->d_table, g->h_table[k], table_bytes_,
+                                    hipMemcpyHostToDevice, stream_);
+      if (e == hipSuccess) e = launch_render_step(lin, D, a, grid, stream_);
+      hipError_t e2 = hipStreamEndCapture(stream_, &g->graph[k]);
+      if (e != hipSuccess) return hip_fail(e, "step capture");
+      if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+      HIP_CHECK(hipGraphInstantiate(&g->exec[k], g->graph[k], nullptr, nullptr, 0));
+    }
     *out = g.get();
     groups_[key] = std::move(g);
     return FASTNERF_OK;
@@ -146,9 +167,11 @@ class GpuExecutor : public fs::Executor {
     if (stream_) (void)hipStreamSynchronize(stream_);
     for (auto &kv : groups_) {
       Group *g = kv.second.get();
-      if (g->exec) (void)hipGraphExecDestroy(g->exec);
-      if (g->graph) (void)hipGraphDestroy(g->graph);
-      if (g->h_table) (void)hipHostFree(g->h_table);
+      for (int k = 0; k < 2; ++k) {
+        if (g->exec[k]) (void)hipGraphExecDestroy(g->exec[k]);
+        if (g->graph[k]) (void)hipGraphDestroy(g->graph[k]);
+        if (g->h_table[k]) (void)hipHostFree(g->h_table[k]);
+      }
       if (g->d_table) (void)hipFree(g->d_table);
       if (g->counter) (void)hipFree(g->counter);
     }
@@ -157,6 +180,9 @@ class GpuExecutor : public fs::Executor {
     caches_ = nullptr;
     if (stream_) (void)hipStreamDestroy(stream_);
     stream_ = nullptr;
+    for (int k = 0; k < 2; ++k)
+      if (done_[k]) (void)hipEventDestroy(done_[k]);
+    done_[0] = done_[1] = nullptr;
   }
 
   std::vector<fastnerf_cache_s *> scenes_;
@@ -165,6 +191,7 @@ class GpuExecutor : public fs::Executor {
   uint8_t *arena_ = nullptr;
   DevCache *caches_ = nullptr;
   hipStream_t stream_ = nullptr;
+  hipEvent_t done_[2] = {nullptr, nullptr};  // end of the last step launched in each slot
   std::map<int, std::unique_ptr<Group>> groups_;
 };
 

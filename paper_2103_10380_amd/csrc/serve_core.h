@@ -8,8 +8,10 @@
 // partly covered continue in the next step, and requests admitted meanwhile
 // join it.
 // An Executor runs each step (the GPU executor launches one persistent kernel;
-// tests use a fake one). A request completes when the step holding its last
-// tile has finished.
+// tests use a fake one). Two steps are in flight at a time: step i+1 is
+// planned and launched before the scheduler waits for step i, so the device
+// gets the next step without waiting for the host. A request completes when
+// every step holding its tiles has finished.
 #pragma once
 #include <stdint.h>
 
@@ -84,7 +86,8 @@ struct Request {
   float near_ = 0, far_ = 0, eps = 0;
   int tiles = 0, next_tile = 0;
   uint64_t bytes = 0, off = 0;
-  bool has_arena = false, cancel_requested = false;
+  int pending = 0;  // launched steps holding tiles of this request, not yet waited for
+  bool has_arena = false, cancel_requested = false, failed = false;
   RState st = RState::Queued;
   Status err = kOk;
   std::chrono::steady_clock::time_point t_submit, t_done;
@@ -105,6 +108,17 @@ class Executor {
   virtual ~Executor() {}
   // Runs every segment of the step to completion; returns kOk or an error.
   virtual Status run(const Step &step, uint64_t arena_base_unused) = 0;
+  // Asynchronous form, slots 0 and 1 used alternately: launch a step, wait for
+  // it later (the step object stays alive until then). The default runs the
+  // step at launch.
+  virtual Status launch(const Step &step, int slot) {
+    done_[slot & 1] = run(step, 0);
+    return kOk;
+  }
+  virtual Status wait(int slot) { return done_[slot & 1]; }
+
+ private:
+  Status done_[2] = {kOk, kOk};
 };
 
 struct Config {
@@ -255,7 +269,7 @@ class Core {
     s->total_tiles = 0;
     std::vector<Request *> act;
     for (Request *r : running_)
-      if (!r->cancel_requested && r->next_tile < r->tiles) act.push_back(r);
+      if (!r->cancel_requested && !r->failed && r->next_tile < r->tiles) act.push_back(r);
     if (act.empty()) return;
     std::vector<int> take(act.size(), 0);
     int budget = cfg_.step_tiles;
@@ -276,50 +290,88 @@ class Core {
     }
   }
 
+  // Retires running requests that are done, cancelled or failed and have no
+  // tiles in a launched step.
+  void retire() {
+    for (auto it = running_.begin(); it != running_.end();) {
+      Request *r = *it;
+      if (r->pending > 0) {
+        ++it;
+      } else if (r->failed) {
+        finish(r, RState::Failed, r->err);
+        it = running_.erase(it);
+      } else if (r->cancel_requested) {
+        finish(r, RState::Canceled, kCanceled);
+        it = running_.erase(it);
+      } else if (r->next_tile >= r->tiles) {
+        finish(r, RState::Done, kOk);
+        it = running_.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+
+  // A launched step has finished (or failed): its requests have one step less
+  // in flight.
+  void step_done(const Step &s, Status st) {
+    for (const Segment &sg : s.segs) {
+      Request *r = sg.req;
+      --r->pending;
+      if (st != kOk && !r->failed) {
+        r->failed = true;
+        r->err = st;
+      }
+    }
+  }
+
   void loop() {
     std::unique_lock<std::mutex> g(mu_);
-    Step step;
+    Step steps[2];
+    bool inflight[2] = {false, false};
+    int cur = 0;
     for (;;) {
-      cv_work_.wait(g, [&] { return stopping_ || !running_.empty() || !queue_.empty(); });
-      if (stopping_ && running_.empty()) break;
+      const int prev = cur ^ 1;
+      if (!inflight[prev])
+        cv_work_.wait(g, [&] { return stopping_ || !running_.empty() || !queue_.empty(); });
+      if (stopping_ && running_.empty() && !inflight[prev]) break;
       admit();
-      // retire cancelled running requests (no step is in flight here)
-      for (auto it = running_.begin(); it != running_.end();) {
-        if ((*it)->cancel_requested) {
-          finish(*it, RState::Canceled, kCanceled);
-          it = running_.erase(it);
+      retire();
+      plan(&steps[cur]);
+      bool launched = false;
+      if (!steps[cur].segs.empty()) {
+        for (const Segment &sg : steps[cur].segs) {
+          sg.req->next_tile += sg.count;
+          ++sg.req->pending;
+        }
+        ++steps_;
+        max_batch_ = std::max<uint64_t>(max_batch_, steps[cur].segs.size());
+        g.unlock();
+        const Status st = ex_->launch(steps[cur], cur);
+        g.lock();
+        if (st != kOk) {
+          step_done(steps[cur], st);
         } else {
-          ++it;
+          inflight[cur] = true;
+          launched = true;
         }
       }
-      plan(&step);
-      if (step.segs.empty()) {
+      if (inflight[prev]) {
+        g.unlock();
+        const Status st = ex_->wait(prev);
+        g.lock();
+        inflight[prev] = false;
+        step_done(steps[prev], st);
+        retire();
+      } else if (!launched) {
+        retire();
         if (running_.empty() && !queue_.empty() && !stopping_) {
           // nothing fits until results are released
           cv_work_.wait_until(g, deadline(5000));
         }
         continue;
       }
-      for (const Segment &sg : step.segs) sg.req->next_tile += sg.count;
-      ++steps_;
-      max_batch_ = std::max<uint64_t>(max_batch_, step.segs.size());
-      g.unlock();
-      const Status st = ex_->run(step, 0);
-      g.lock();
-      for (auto it = running_.begin(); it != running_.end();) {
-        Request *r = *it;
-        bool in_step = false;
-        for (const Segment &sg : step.segs) in_step |= sg.req == r;
-        if (st != kOk && in_step) {
-          finish(r, RState::Failed, st);
-          it = running_.erase(it);
-        } else if (r->next_tile >= r->tiles && !r->cancel_requested) {
-          finish(r, RState::Done, kOk);
-          it = running_.erase(it);
-        } else {
-          ++it;
-        }
-      }
+      if (launched) cur ^= 1;
     }
   }
 
