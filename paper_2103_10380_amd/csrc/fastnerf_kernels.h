@@ -9,8 +9,9 @@ int render_occupancy(int fmt, bool lin, int D, bool sparse);
 // Tile queues of a render launch and the spacing of their counters (uints):
 // the counter buffer of a stream holds kQueueCounters uints.
 constexpr int kQueueCounters = 32 * 32;
-int render_step_occupancy(bool lin, int D);
-hipError_t launch_render_step(bool lin, int D, const RenderArgs &a, int grid, hipStream_t s);
+int render_step_occupancy(int fmt, bool lin, int D);
+hipError_t launch_render_step(int fmt, bool lin, int D, const RenderArgs &a, int grid,
+                              hipStream_t s);
 hipError_t launch_render(int fmt, bool lin, const RenderArgs &a, int grid, hipStream_t s);
 // Voxel traversal (views with N = 0; nearest lookups, k <= 1024).
 int render_vox_occupancy(int fmt, int D);

@@ -650,16 +650,14 @@ __global__ void __launch_bounds__(kBlock) k_render_vox(RenderArgs a) {
   queue_retire(Q, lane);
 }
 
-// Serving step: tile ranges of many views over several resident caches of any
-// storage format, in one launch; the step's size is read from device memory so
-// the launch can be replayed from a captured graph.
-// Nearest lookups with up to 8 components are compiled for 3 waves per SIMD
-// (the four formats' code in one kernel would otherwise leave 2).
-constexpr int step_waves(int maxd, bool lin) { return maxd <= 8 && !lin ? 3 : 1; }
-
-template <int MAXD, bool LIN>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves(MAXD, LIN))))
-k_render_step(RenderArgs a) {
+// Serving step: tile ranges of many views over several resident caches of one
+// storage format, in one launch (one per format present); the step's size is
+// read from device memory so the launch can be replayed from a captured graph.
+// Compiled for the waves per SIMD of the batched kernel of the same format.
+template <int FMT, int MAXD, bool LIN>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(render_waves(FMT, MAXD, LIN))))
+    k_render_step(RenderArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int total = __builtin_amdgcn_readfirstlane(a.dyn_total[0]);
   const int nviews = __builtin_amdgcn_readfirstlane(a.dyn_total[1]);
@@ -669,13 +667,7 @@ k_render_step(RenderArgs a) {
     if (tile < 0) break;
     const DevView V = a.views[view_of_tile(a, tile, nviews)];
     const DevCache c = a.caches[V.scene];
-    const int lt = tile - V.tile_begin + V.tile_offset;
-    switch (c.fmt) {
-      case 0: render_tile<0, MAXD, LIN>(a, c, V, lt, lane); break;
-      case 1: render_tile<1, MAXD, LIN>(a, c, V, lt, lane); break;
-      case 2: render_tile<2, MAXD, LIN>(a, c, V, lt, lane); break;
-      default: render_tile<3, MAXD, LIN>(a, c, V, lt, lane); break;
-    }
+    render_tile<FMT, MAXD, LIN>(a, c, V, tile - V.tile_begin + V.tile_offset, lane);
   }
   queue_retire(Q, lane);
 }
@@ -1016,40 +1008,58 @@ hipError_t launch_readback_f(const DevCache &c, float *sigma, float *u, hipStrea
 
 namespace {
 
-template <int MAXD>
+template <int FMT, int MAXD>
 hipError_t launch_step_t(bool lin, const RenderArgs &a, int grid, hipStream_t s) {
-  if (lin) hipLaunchKernelGGL((k_render_step<MAXD, true>), dim3(grid), dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_render_step<MAXD, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  if (lin) hipLaunchKernelGGL((k_render_step<FMT, MAXD, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_render_step<FMT, MAXD, false>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-template <int MAXD>
+template <int FMT, int MAXD>
 int step_occupancy_t(bool lin) {
   int nb = 0;
   const hipError_t e =
-      lin ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<MAXD, true>, kBlock, 0)
-          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<MAXD, false>, kBlock, 0);
+      lin ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<FMT, MAXD, true>,
+                                                         kBlock, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render_step<FMT, MAXD, false>,
+                                                         kBlock, 0);
   return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+// The kernel for (format, lookup, component-count class); a null launch
+// argument asks for the resident blocks per CU instead.
+template <int FMT>
+hipError_t step_dispatch(bool lin, int D, const RenderArgs *a, int grid, hipStream_t s, int *occ) {
+  switch (maxd_class(D)) {
+    case 4: return a ? launch_step_t<FMT, 4>(lin, *a, grid, s) : (*occ = step_occupancy_t<FMT, 4>(lin), hipSuccess);
+    case 8: return a ? launch_step_t<FMT, 8>(lin, *a, grid, s) : (*occ = step_occupancy_t<FMT, 8>(lin), hipSuccess);
+    default: return a ? launch_step_t<FMT, 16>(lin, *a, grid, s) : (*occ = step_occupancy_t<FMT, 16>(lin), hipSuccess);
+  }
+}
+
+hipError_t step_dispatch_fmt(int fmt, bool lin, int D, const RenderArgs *a, int grid,
+                             hipStream_t s, int *occ) {
+  switch (fmt) {
+    case 0: return step_dispatch<0>(lin, D, a, grid, s, occ);
+    case 1: return step_dispatch<1>(lin, D, a, grid, s, occ);
+    case 2: return step_dispatch<2>(lin, D, a, grid, s, occ);
+    default: return step_dispatch<3>(lin, D, a, grid, s, occ);
+  }
 }
 
 }  // namespace
 
-// D selects the kernel's component-count class (maxd_class), which must be the
-// class of every cache of the step.
-hipError_t launch_render_step(bool lin, int D, const RenderArgs &a, int grid, hipStream_t s) {
-  switch (maxd_class(D)) {
-    case 4: return launch_step_t<4>(lin, a, grid, s);
-    case 8: return launch_step_t<8>(lin, a, grid, s);
-    default: return launch_step_t<16>(lin, a, grid, s);
-  }
+// fmt and D select the kernel's storage format and component-count class
+// (maxd_class), which must be those of every cache of the step.
+hipError_t launch_render_step(int fmt, bool lin, int D, const RenderArgs &a, int grid,
+                              hipStream_t s) {
+  return step_dispatch_fmt(fmt, lin, D, &a, grid, s, nullptr);
 }
 
-int render_step_occupancy(bool lin, int D) {
-  switch (maxd_class(D)) {
-    case 4: return step_occupancy_t<4>(lin);
-    case 8: return step_occupancy_t<8>(lin);
-    default: return step_occupancy_t<16>(lin);
-  }
+int render_step_occupancy(int fmt, bool lin, int D) {
+  int occ = 1;
+  (void)step_dispatch_fmt(fmt, lin, D, nullptr, 0, nullptr, &occ);
+  return occ;
 }
 
 int render_occupancy(int fmt, bool lin, int D, bool sparse) {

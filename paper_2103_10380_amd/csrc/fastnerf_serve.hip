@@ -69,7 +69,7 @@ class GpuExecutor : public fs::Executor {
   // reuses it, so the pinned table of a step in flight is never rewritten).
   fs::Status launch(const fs::Step &step, int slot) override {
     slot &= 1;
-    // one launch per (interpolation, component-count) class present
+    // one launch per (format, interpolation, component-count) group present
     std::map<int, std::vector<const fs::Segment *>> groups;
     for (const auto &sg : step.segs) {
       const fastnerf_cache_s *c = scenes_[sg.req->scene];
@@ -119,9 +119,11 @@ class GpuExecutor : public fs::Executor {
     hipGraphExec_t exec[2] = {nullptr, nullptr};
   };
 
-  // (interpolation, component-count class): the class fixes the record layout
+  // (storage format, interpolation, component-count class): each has its own
+  // step kernel (the class fixes the record layout)
   static int group_key(const fastnerf_cache_s *c) {
-    return (c->desc.pos_interp == FASTNERF_LINEAR ? 4 : 0) + maxd_class(c->desc.D) / 8;
+    return (int)c->desc.storage * 8 + (c->desc.pos_interp == FASTNERF_LINEAR ? 4 : 0) +
+           maxd_class(c->desc.D) / 8;
   }
 
   fastnerf_status group(int key, Group **out) {
@@ -138,9 +140,10 @@ class GpuExecutor : public fs::Executor {
     HIP_CHECK(hipMalloc(&g->d_table, table_bytes_));
     HIP_CHECK(hipMalloc(&g->counter, kQueueCounters * sizeof(unsigned)));
     HIP_CHECK(hipMemset(g->counter, 0, kQueueCounters * sizeof(unsigned)));
+    const int fmt = key >> 3;
     const bool lin = key & 4;
     const int D = (key & 3) == 0 ? 4 : ((key & 3) == 1 ? 8 : 16);
-    const int grid = cus_ * render_step_occupancy(lin, D);
+    const int grid = cus_ * render_step_occupancy(fmt, lin, D);
     RenderArgs a;
     memset(&a, 0, sizeof a);
     a.views = reinterpret_cast<const DevView *>(g->d_table + sizeof(StepHeader));
@@ -152,7 +155,7 @@ class GpuExecutor : public fs::Executor {
       HIP_CHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipMemcpyAsync(g->d_table, g->h_table[k], table_bytes_,
                                     hipMemcpyHostToDevice, stream_);
-      if (e == hipSuccess) e = launch_render_step(lin, D, a, grid, stream_);
+      if (e == hipSuccess) e = launch_render_step(fmt, lin, D, a, grid, stream_);
       hipError_t e2 = hipStreamEndCapture(stream_, &g->graph[k]);
       if (e != hipSuccess) return hip_fail(e, "step capture");
       if (e2 != hipSuccess) return hip_fail(e2, "end capture");
