@@ -620,8 +620,8 @@ def main():
         print(json.dumps(pmc_traffic(*args.pmc_traffic), indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build "
-              "renders on a single MI355X; multi-GPU sharding is a design note only)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the renderer "
+              "runs on a single MI355X; sharding across GPUs is described, not built)",
               file=sys.stderr)
         sys.exit(2)
 
