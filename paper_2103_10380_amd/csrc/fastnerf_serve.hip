@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <vector>
 
 #include "fastnerf.h"
@@ -71,9 +72,11 @@ class GpuExecutor : public fs::Executor {
     slot &= 1;
     // one launch per (format, interpolation, component-count) group present
     std::map<int, std::vector<const fs::Segment *>> groups;
+    std::set<int> used;
     for (const auto &sg : step.segs) {
       const fastnerf_cache_s *c = scenes_[sg.req->scene];
       groups[group_key(c)].push_back(&sg);
+      used.insert(sg.req->scene);
     }
     for (auto &kv : groups) {
       Group *g = nullptr;
@@ -96,10 +99,11 @@ class GpuExecutor : public fs::Executor {
       hh->total = tb;
       hh->nviews = n;
       if (hipGraphLaunch(g->exec[slot], stream_) != hipSuccess) return fs::kDevice;
-      for (const fs::Segment *sg : kv.second)
-        if (hipEventRecord(scenes_[sg->req->scene]->last_use, stream_) != hipSuccess)
-          return fs::kDevice;
     }
+    // each scene's last use, once per step (a marker per request segment had
+    // put up to max_inflight packets between the step's kernels)
+    for (int sc : used)
+      if (hipEventRecord(scenes_[sc]->last_use, stream_) != hipSuccess) return fs::kDevice;
     return hipEventRecord(done_[slot], stream_) == hipSuccess ? fs::kOk : fs::kDevice;
   }
 

@@ -125,9 +125,10 @@ struct Config {
   uint64_t arena_bytes = 0;
   int max_inflight = 16;
   int queue_cap = 4096;
-  // about 4M rays: several typical requests per step, so the per-step launch
-  // and synchronisation are amortised when the server is loaded
-  int step_tiles = 1 << 16;
+  // about 16M rays: when the server is loaded a step holds many requests, so
+  // the gap before each step's launches (graph replay with its table copy) is
+  // amortised; a lone request of up to 1920x1080 (32,400 tiles) is one step
+  int step_tiles = 1 << 18;
 };
 
 class Core {
