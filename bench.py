@@ -440,6 +440,50 @@ def voxel_sweep(fn, main=None, ks=(256, 384, 512, 768), nviews=8, reps=3, pix=20
 SERVE_RES = [(400, 400), (800, 800), (1280, 720), (1920, 1080)]
 
 
+def serve_offline(fn, caches, n_req, n_warm, seed=3, N=192, eps=1e-4, chunk=32):
+    """The measured requests of serve_poisson (the same draws) rendered without
+    the server: per scene, in submission order, batched launches of up to
+    `chunk` views (the server's max_inflight), back to back on one stream. The
+    rate the server's steps are compared with."""
+    import torch
+    import synth
+    rng = np.random.default_rng(seed)
+    per_scene = [[] for _ in caches]
+    for i in range(n_warm + n_req):
+        rng.exponential(1.0)
+        W, H = SERVE_RES[rng.integers(len(SERVE_RES))]
+        v = synth.orbit_view(rng.uniform(3.0, 5.0), rng.uniform(0, 2 * np.pi),
+                             rng.uniform(-1.0, 1.0), W, H, 0.0, 100.0)
+        scene = int(rng.integers(len(caches)))
+        if i >= n_warm:
+            per_scene[scene].append(v)
+    batches = [(c, vs[j:j + chunk]) for c, vs in zip(caches, per_scene)
+               for j in range(0, len(vs), chunk)]
+    flat = torch.empty(chunk * max(w * h for w, h in SERVE_RES) * 4, dtype=torch.float32,
+                       device="cuda")
+
+    def outs_for(vs):
+        out, off = [], 0
+        for v in vs:
+            out.append(flat.narrow(0, off, v.H * v.W * 4).view(v.H, v.W, 4))
+            off += v.H * v.W * 4
+        return out
+    outs = [outs_for(vs) for _, vs in batches]
+
+    def run():
+        for (c, vs), o in zip(batches, outs):
+            fn.render_batch(c, vs, N, eps, outs=o)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rays = sum(v.H * v.W for _, vs in batches for v in vs)
+    return {"requests": n_req, "launches": len(batches), "views_per_launch_max": chunk,
+            "frames_per_s": round(n_req / el, 1), "mrays_per_s": round(rays / el / 1e6, 1)}
+
+
 def serve_poisson(fn, caches, lam, n_req, n_warm, seed=3, N=192, eps=1e-4):
     """Poisson arrivals at lam requests/s over the resident caches: each request
     draws a scene, a resolution from SERVE_RES and a pose (r U[3,5], az U[0,2pi),
@@ -511,6 +555,34 @@ def serving_scenes(fn):
         log(f"serving scene k={k} {st} seed {seed}: occupancy {occ:.4f}")
         caches.append(cs[st])
     return caches
+
+
+def step_gaps(path, match="k_render_step", skip=0.2):
+    """Busy fraction and gaps of the serving step kernels in a rocprofv3 kernel
+    trace (CSV): the first `skip` of the launches (warm-up, ramp) is left out;
+    a gap is the idle time before a launch after every earlier one ended."""
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True))[0]
+    rows = [r for r in csv.DictReader(open(f)) if match in r["Kernel_Name"]]
+    st = np.array([int(r["Start_Timestamp"]) for r in rows], np.int64)
+    en = np.array([int(r["End_Timestamp"]) for r in rows], np.int64)
+    o = np.argsort(st)
+    st, en = st[o], en[o]
+    a = int(len(st) * skip)
+    st, en = st[a:], en[a:]
+    dur = (en - st) / 1e3
+    span = (en.max() - st[0]) / 1e3
+    ends = np.maximum.accumulate(en)
+    gaps = np.maximum(st[1:] - ends[:-1], 0) / 1e3
+    lines = [f"# {match}: {len(rows)} launches, the last {len(st)} analysed",
+             f"window {span / 1e3:.1f} ms, busy {1 - gaps.sum() / span:.3f} of it"]
+    for q in (10, 50, 90, 99):
+        lines.append(f"duration p{q}: {np.percentile(dur, q):.1f} us; "
+                     f"gap p{q}: {np.percentile(gaps, q):.1f} us")
+    lines.append(f"mean duration {dur.mean():.1f} us, mean gap {gaps.mean():.1f} us, "
+                 f"total gap {gaps.sum() / 1e3:.1f} ms")
+    return "\n".join(lines)
 
 
 def summarize_profile(paths, match=("k_render", "k_bake", "neg_kernel")):
@@ -603,18 +675,25 @@ def main():
                     help="only the serving workload: four resident scenes, Poisson arrivals "
                          "at 50/100/200/400/1600/6400/12800 requests/s (one JSON line)")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rates", default="50,100,200,400,1600,6400,12800",
+                    help="Poisson arrival rates (requests/s) of --serving")
     ap.add_argument("--bake", action="store_true",
                     help="only the cache bake of the paper's networks (one JSON line)")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-view latency launches (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision sweep, the batched launch and the serving sample")
+    ap.add_argument("--step-gaps", metavar="DIR",
+                    help="busy fraction and gaps of the serving step kernels in a kernel trace")
     ap.add_argument("--pmc-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the render kernel's calibrated HBM bytes per launch (JSON) "
                          "from FETCH_SIZE and WRITE_SIZE runs made with --calibrate-copy")
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile))
+        return
+    if args.step_gaps:
+        print(step_gaps(args.step_gaps))
         return
     if args.pmc_traffic:
         print(json.dumps(pmc_traffic(*args.pmc_traffic), indent=1))
@@ -636,11 +715,14 @@ def main():
         caches = serving_scenes(fn)
         log(f"serving scenes built in {time.perf_counter() - t0:.1f}s")
         rows = []
-        for lam in (50, 100, 200, 400, 1600, 6400, 12800):
+        for lam in [int(x) for x in args.serve_rates.split(",")]:
             r = serve_poisson(fn, caches, lam, args.serve_requests, 100)
             log(f"lambda {lam}: p50 {r['latency_ms_p50']} ms p99 {r['latency_ms_p99']} ms, "
                 f"{r['frames_per_s']} frames/s")
             rows.append(r)
+        off = serve_offline(fn, caches, args.serve_requests, 100)
+        log(f"same requests without the server: {off['frames_per_s']} frames/s, "
+            f"{off['mrays_per_s']} Mrays/s")
         print(json.dumps({
             "metric": "serving latency (p50/p99) under Poisson arrivals", "unit": "ms",
             "n_gpus": 1, "data": "synthetic",
@@ -649,7 +731,8 @@ def main():
                                    "requests of 400^2/800^2/1280x720/1920x1080 at random "
                                    "poses, N=192 in the box, eps=1e-4, seed 3",
                        "warmup_requests": 100, "requests_per_rate": args.serve_requests},
-            "rates": rows, "kernel_digest": kernel_digest()}), flush=True)
+            "rates": rows, "offline_same_mix": off, "kernel_digest": kernel_digest()}),
+              flush=True)
         return
 
     if args.bake:
