@@ -44,9 +44,6 @@ class GpuExecutor : public fs::Executor {
     scenes_ = scenes;
     max_views_ = max_views;
     arena_ = arena;
-    HIP_CHECK(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
-    for (int k = 0; k < 2; ++k)
-      HIP_CHECK(hipEventCreateWithFlags(&done_[k], hipEventDisableTiming));
     std::vector<DevCache> dc;
     for (auto *c : scenes) dc.push_back(dev_cache(c));
     HIP_CHECK(hipMalloc(&caches_, sizeof(DevCache) * dc.size()));
@@ -68,22 +65,25 @@ class GpuExecutor : public fs::Executor {
   // Enqueues the step's launches with the descriptor tables of slot `slot`
   // (0 or 1: the scheduler alternates them and waits for a slot before it
   // reuses it, so the pinned table of a step in flight is never rewritten).
+  // Each group runs on its own stream, so one group's tail overlaps the other
+  // groups' work; a group's steps stay in order on its stream.
   fs::Status launch(const fs::Step &step, int slot) override {
     slot &= 1;
     // one launch per (format, interpolation, component-count) group present
     std::map<int, std::vector<const fs::Segment *>> groups;
-    std::set<int> used;
     for (const auto &sg : step.segs) {
       const fastnerf_cache_s *c = scenes_[sg.req->scene];
       groups[group_key(c)].push_back(&sg);
-      used.insert(sg.req->scene);
     }
+    std::vector<Group *> &launched = launched_[slot];
+    launched.clear();
     for (auto &kv : groups) {
       Group *g = nullptr;
       if (group(kv.first, &g) != FASTNERF_OK) return fs::kDevice;
       StepHeader *hh = reinterpret_cast<StepHeader *>(g->h_table[slot]);
       DevView *hv = reinterpret_cast<DevView *>(g->h_table[slot] + sizeof(StepHeader));
       int tb = 0, n = 0;
+      std::set<int> used;
       for (const fs::Segment *sg : kv.second) {
         const fs::Request *r = sg->req;
         fastnerf_cache_s *c = scenes_[r->scene];
@@ -95,27 +95,35 @@ class GpuExecutor : public fs::Executor {
         hv[n].lim = eps_limit(r->eps);
         tb += sg->count;
         ++n;
+        used.insert(r->scene);
       }
       hh->total = tb;
       hh->nviews = n;
-      if (hipGraphLaunch(g->exec[slot], stream_) != hipSuccess) return fs::kDevice;
+      if (hipGraphLaunch(g->exec[slot], g->stream) != hipSuccess) return fs::kDevice;
+      launched.push_back(g);
+      // each scene's last use, once per step (a marker per request segment had
+      // put up to max_inflight packets between the step's kernels)
+      for (int sc : used)
+        if (hipEventRecord(scenes_[sc]->last_use, g->stream) != hipSuccess) return fs::kDevice;
+      if (hipEventRecord(g->done[slot], g->stream) != hipSuccess) return fs::kDevice;
     }
-    // each scene's last use, once per step (a marker per request segment had
-    // put up to max_inflight packets between the step's kernels)
-    for (int sc : used)
-      if (hipEventRecord(scenes_[sc]->last_use, stream_) != hipSuccess) return fs::kDevice;
-    return hipEventRecord(done_[slot], stream_) == hipSuccess ? fs::kOk : fs::kDevice;
+    return fs::kOk;
   }
 
   fs::Status wait(int slot) override {
-    return hipEventSynchronize(done_[slot & 1]) == hipSuccess ? fs::kOk : fs::kDevice;
+    for (Group *g : launched_[slot & 1])
+      if (hipEventSynchronize(g->done[slot & 1]) != hipSuccess) return fs::kDevice;
+    return fs::kOk;
   }
 
  private:
-  // Per group: a pinned descriptor table and a captured graph (table copy,
-  // then the step kernel) for each of the two slots; the device table and the
-  // queue counters are shared, since the steps run in order on one stream.
+  // Per group: its stream, a pinned descriptor table, a captured graph (table
+  // copy, then the step kernel) and an end-of-launch event for each of the two
+  // slots; the device table and the queue counters are shared by the slots,
+  // since the group's steps run in order on its stream.
   struct Group {
+    hipStream_t stream = nullptr;
+    hipEvent_t done[2] = {nullptr, nullptr};    // end of the group's last launch in each slot
     uint8_t *h_table[2] = {nullptr, nullptr};  // pinned
     uint8_t *d_table = nullptr;
     unsigned *counter = nullptr;
@@ -137,7 +145,20 @@ class GpuExecutor : public fs::Executor {
       return FASTNERF_OK;
     }
     std::unique_ptr<Group> g(new Group());
+    const fastnerf_status st = build_group(key, g.get());
+    if (st != FASTNERF_OK) {
+      destroy_group(g.get());
+      return st;
+    }
+    *out = g.get();
+    groups_[key] = std::move(g);
+    return FASTNERF_OK;
+  }
+
+  fastnerf_status build_group(int key, Group *g) {
+    HIP_CHECK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
     for (int k = 0; k < 2; ++k) {
+      HIP_CHECK(hipEventCreateWithFlags(&g->done[k], hipEventDisableTiming));
       HIP_CHECK(hipHostMalloc(&g->h_table[k], table_bytes_, hipHostMallocDefault));
       memset(g->h_table[k], 0, table_bytes_);
     }
@@ -156,40 +177,38 @@ class GpuExecutor : public fs::Executor {
     a.counter = g->counter;
     a.nwaves = (unsigned)grid * (kBlock / kWave);
     for (int k = 0; k < 2; ++k) {
-      HIP_CHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+      HIP_CHECK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipMemcpyAsync(g->d_table, g->h_table[k], table_bytes_,
-                                    hipMemcpyHostToDevice, stream_);
-      if (e == hipSuccess) e = launch_render_step(fmt, lin, D, a, grid, stream_);
-      hipError_t e2 = hipStreamEndCapture(stream_, &g->graph[k]);
+                                    hipMemcpyHostToDevice, g->stream);
+      if (e == hipSuccess) e = launch_render_step(fmt, lin, D, a, grid, g->stream);
+      hipError_t e2 = hipStreamEndCapture(g->stream, &g->graph[k]);
       if (e != hipSuccess) return hip_fail(e, "step capture");
       if (e2 != hipSuccess) return hip_fail(e2, "end capture");
       HIP_CHECK(hipGraphInstantiate(&g->exec[k], g->graph[k], nullptr, nullptr, 0));
     }
-    *out = g.get();
-    groups_[key] = std::move(g);
+    // the counters are cleared before the first launch that uses them
+    HIP_CHECK(hipDeviceSynchronize());
     return FASTNERF_OK;
   }
 
-  void free_all() {
-    if (stream_) (void)hipStreamSynchronize(stream_);
-    for (auto &kv : groups_) {
-      Group *g = kv.second.get();
-      for (int k = 0; k < 2; ++k) {
-        if (g->exec[k]) (void)hipGraphExecDestroy(g->exec[k]);
-        if (g->graph[k]) (void)hipGraphDestroy(g->graph[k]);
-        if (g->h_table[k]) (void)hipHostFree(g->h_table[k]);
-      }
-      if (g->d_table) (void)hipFree(g->d_table);
-      if (g->counter) (void)hipFree(g->counter);
+  static void destroy_group(Group *g) {
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    for (int k = 0; k < 2; ++k) {
+      if (g->exec[k]) (void)hipGraphExecDestroy(g->exec[k]);
+      if (g->graph[k]) (void)hipGraphDestroy(g->graph[k]);
+      if (g->h_table[k]) (void)hipHostFree(g->h_table[k]);
+      if (g->done[k]) (void)hipEventDestroy(g->done[k]);
     }
+    if (g->d_table) (void)hipFree(g->d_table);
+    if (g->counter) (void)hipFree(g->counter);
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+  }
+
+  void free_all() {
+    for (auto &kv : groups_) destroy_group(kv.second.get());
     groups_.clear();
     if (caches_) (void)hipFree(caches_);
     caches_ = nullptr;
-    if (stream_) (void)hipStreamDestroy(stream_);
-    stream_ = nullptr;
-    for (int k = 0; k < 2; ++k)
-      if (done_[k]) (void)hipEventDestroy(done_[k]);
-    done_[0] = done_[1] = nullptr;
   }
 
   std::vector<fastnerf_cache_s *> scenes_;
@@ -197,9 +216,8 @@ class GpuExecutor : public fs::Executor {
   size_t table_bytes_ = 0;
   uint8_t *arena_ = nullptr;
   DevCache *caches_ = nullptr;
-  hipStream_t stream_ = nullptr;
-  hipEvent_t done_[2] = {nullptr, nullptr};  // end of the last step launched in each slot
   std::map<int, std::unique_ptr<Group>> groups_;
+  std::vector<Group *> launched_[2];  // groups launched in each slot's last step
 };
 
 }  // namespace
