@@ -180,8 +180,12 @@ double fastnerf_model_bytes(double alpha, int64_t k, int64_t l, int32_t D, doubl
 /* A continuous-batching render server over resident caches. Requests are
  * admitted while their output fits the arena (bytes of device memory the
  * server owns) and fewer than max_inflight are running; every step renders
- * all admitted requests' tiles in one persistent launch, replayed as a HIP
- * graph. Requests that arrive while others run join at the next step. */
+ * the running requests' tiles, an equal share each of a tile budget, in one
+ * persistent launch per (storage format, lookup, component class) group,
+ * replayed as a HIP graph on that group's own stream. Requests that arrive
+ * while others run join at the next step. The server's streams, graphs and
+ * pinned tables are created here and on a group's first use, and released by
+ * destroy. */
 fastnerf_status fastnerf_server_create(const fastnerf_cache *scenes, int32_t nscenes,
                                        uint64_t arena_bytes, int32_t max_inflight,
                                        fastnerf_server *out);

@@ -164,7 +164,8 @@ class GpuExecutor : public fs::Executor {
     }
     HIP_CHECK(hipMalloc(&g->d_table, table_bytes_));
     HIP_CHECK(hipMalloc(&g->counter, kQueueCounters * sizeof(unsigned)));
-    HIP_CHECK(hipMemset(g->counter, 0, kQueueCounters * sizeof(unsigned)));
+    // cleared on the group's stream, ahead of every launch of its graphs
+    HIP_CHECK(hipMemsetAsync(g->counter, 0, kQueueCounters * sizeof(unsigned), g->stream));
     const int fmt = key >> 3;
     const bool lin = key & 4;
     const int D = (key & 3) == 0 ? 4 : ((key & 3) == 1 ? 8 : 16);
@@ -186,8 +187,6 @@ class GpuExecutor : public fs::Executor {
       if (e2 != hipSuccess) return hip_fail(e2, "end capture");
       HIP_CHECK(hipGraphInstantiate(&g->exec[k], g->graph[k], nullptr, nullptr, 0));
     }
-    // the counters are cleared before the first launch that uses them
-    HIP_CHECK(hipDeviceSynchronize());
     return FASTNERF_OK;
   }
 
