@@ -1,8 +1,9 @@
 // Render server: the C ABI over the continuous-batching scheduler
 // (serve_core.h) with a GPU executor. Every step is one persistent launch of
-// k_render_step over the tile ranges of all scheduled requests, whatever their
-// scene or storage format; the launch and the copy of its descriptor table are
-// captured once into a HIP graph and replayed each step.
+// k_render_step per (storage format, lookup, component class) group over the
+// tile ranges of that group's scheduled requests, whatever their scene; each
+// group's launch and the copy of its descriptor table are captured once into a
+// HIP graph and replayed each step on the group's own stream.
 #include <string.h>
 
 #include <map>

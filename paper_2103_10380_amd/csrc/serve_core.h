@@ -7,8 +7,8 @@
 // from the running requests, an equal share each; requests that are only
 // partly covered continue in the next step, and requests admitted meanwhile
 // join it.
-// An Executor runs each step (the GPU executor launches one persistent kernel;
-// tests use a fake one). Two steps are in flight at a time: step i+1 is
+// An Executor runs each step (the GPU executor launches one persistent kernel
+// per storage-format group; tests use a fake one). Two steps are in flight at a time: step i+1 is
 // planned and launched before the scheduler waits for step i, so the device
 // gets the next step without waiting for the host. A request completes when
 // every step holding its tiles has finished.
