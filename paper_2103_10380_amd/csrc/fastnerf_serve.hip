@@ -78,9 +78,16 @@ class GpuExecutor : public fs::Executor {
     }
     std::vector<Group *> &launched = launched_[slot];
     launched.clear();
+    // on a failure the step's requests are failed and their memory may be
+    // reused: the groups already launched finish first
+    auto fail = [&launched]() {
+      for (Group *x : launched) (void)hipStreamSynchronize(x->stream);
+      launched.clear();
+      return fs::kDevice;
+    };
     for (auto &kv : groups) {
       Group *g = nullptr;
-      if (group(kv.first, &g) != FASTNERF_OK) return fs::kDevice;
+      if (group(kv.first, &g) != FASTNERF_OK) return fail();
       StepHeader *hh = reinterpret_cast<StepHeader *>(g->h_table[slot]);
       DevView *hv = reinterpret_cast<DevView *>(g->h_table[slot] + sizeof(StepHeader));
       int tb = 0, n = 0;
@@ -100,21 +107,23 @@ class GpuExecutor : public fs::Executor {
       }
       hh->total = tb;
       hh->nviews = n;
-      if (hipGraphLaunch(g->exec[slot], g->stream) != hipSuccess) return fs::kDevice;
       launched.push_back(g);
+      if (hipGraphLaunch(g->exec[slot], g->stream) != hipSuccess) return fail();
       // each scene's last use, once per step (a marker per request segment had
       // put up to max_inflight packets between the step's kernels)
       for (int sc : used)
-        if (hipEventRecord(scenes_[sc]->last_use, g->stream) != hipSuccess) return fs::kDevice;
-      if (hipEventRecord(g->done[slot], g->stream) != hipSuccess) return fs::kDevice;
+        if (hipEventRecord(scenes_[sc]->last_use, g->stream) != hipSuccess) return fail();
+      if (hipEventRecord(g->done[slot], g->stream) != hipSuccess) return fail();
     }
     return fs::kOk;
   }
 
+  // Waits for every group of the slot's step, also after one of them failed.
   fs::Status wait(int slot) override {
+    fs::Status st = fs::kOk;
     for (Group *g : launched_[slot & 1])
-      if (hipEventSynchronize(g->done[slot & 1]) != hipSuccess) return fs::kDevice;
-    return fs::kOk;
+      if (hipEventSynchronize(g->done[slot & 1]) != hipSuccess) st = fs::kDevice;
+    return st;
   }
 
  private:
