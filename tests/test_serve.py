@@ -71,3 +71,32 @@ def test_request_larger_than_arena_is_rejected():
             srv.submit(5, v.K, v.c2w, 8, 8, v.near, v.far, 64, 1e-4)
     finally:
         srv.destroy()
+
+
+def test_requests_split_across_steps_equal_standalone_renders():
+    """Two 4096x4096 requests (262,144 tiles each: more than a step's share of
+    the tile budget when they run together) in the FP16 and FP8 scenes, with
+    small FP32 requests among them: the large ones span several steps in both
+    slots while the format groups run concurrently; every result equals its
+    standalone render bitwise."""
+    import torch
+    import paper_2103_10380_amd as fn
+    caches = _scenes()
+    reqs = [(0, synth.orbit_view(3.0, 0.3, 0.2, 4096, 4096, 0.0, 100.0)),
+            (1, synth.orbit_view(3.5, 2.1, -0.4, 4096, 4096, 0.0, 100.0))]
+    reqs += [(2, synth.orbit_view(3.0 + 0.2 * i, 0.5 * i, 0.1, 64 + 8 * i, 48, 0.0, 100.0))
+             for i in range(4)]
+    srv = fn.Server(caches, arena_bytes=1 << 30, max_inflight=8)
+    try:
+        tickets = [srv.submit(s, v.K, v.c2w, v.H, v.W, v.near, v.far, 64, 1e-4) for s, v in reqs]
+        for (s, v), t in zip(reqs, tickets):
+            got, _ = srv.result(t, v.H, v.W)
+            alone = fn.render(caches[s], v.K, v.c2w, v.H, v.W, v.near, v.far, 64, 1e-4)
+            torch.cuda.synchronize()
+            assert torch.equal(got, alone), (s, v.H, v.W)
+            del got, alone
+        st = srv.stats()
+        assert st["completed"] == len(reqs)
+        assert st["steps"] >= 3, st  # the large requests were split
+    finally:
+        srv.destroy()
