@@ -890,6 +890,15 @@ def main():
             r["scenes"] = "paper-scale k=768 FP16 and FP8 caches of this run"
             line["serving_sample"] = r
             log(f"serving sample: p50 {r['latency_ms_p50']} ms p99 {r['latency_ms_p99']} ms")
+            # the same scenes with arrivals faster than the GPU can serve them,
+            # beside the same requests rendered without the server
+            pair = [caches["f16"], caches["fp8"]]
+            r = serve_poisson(fn, pair, 12800, 1000, 100)
+            r["scenes"] = "paper-scale k=768 FP16 and FP8 caches of this run"
+            r["offline_same_mix"] = serve_offline(fn, pair, 1000, 100)
+            line["serving_saturated"] = r
+            log(f"serving at 12800 req/s: {r['frames_per_s']} frames/s, offline "
+                f"{r['offline_same_mix']['frames_per_s']} frames/s")
         line["voxel_traversal"] = voxel_sweep(fn, (spec.k, caches.get("f32"), sparse, beta))
         # level of detail: the level the library picks for the orbit's camera
         # among the swept resolutions, and its cost from the sweep
