@@ -1,0 +1,82 @@
+"""Host-side analysis in bench.py that the committed profiles rest on, on
+synthetic rocprofv3 CSV files: the step-kernel gap analysis and the HBM
+traffic from calibrated FETCH_SIZE / WRITE_SIZE counters."""
+import csv
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def _trace(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_kernel_trace.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writerows(rows)
+
+
+def test_step_gaps_serial_launches(tmp_path):
+    # ten 100 us step kernels with 20 us gaps, and an unrelated kernel that
+    # must be ignored; skip=0 keeps every launch
+    rows, t = [], 0
+    for i in range(10):
+        rows.append(["void fnr::k_render_step<1, 8, false>(fnr::RenderArgs)", t, t + 100_000])
+        t += 120_000
+    rows.append(["void fnr::k_render<0, 8, false>(fnr::RenderArgs)", 0, 5_000_000])
+    _trace(str(tmp_path), rows)
+    out = bench.step_gaps(str(tmp_path), skip=0.0)
+    # window = 9 * 120 + 100 = 1180 us, gaps 9 * 20 = 180 us
+    assert "window 1.2 ms, busy 0.847 of it" in out
+    assert "mean duration 100.0 us, mean gap 20.0 us, total gap 0.2 ms" in out
+    assert "10 launches, the last 10 analysed" in out
+
+
+def test_step_gaps_overlapping_streams(tmp_path):
+    # two streams: A runs 0-100, 150-250; B runs 50-180 (overlaps both):
+    # the union is 0-250 with no idle time
+    rows = [["k_render_step<1, 8, false>", 0, 100_000],
+            ["k_render_step<3, 8, false>", 50_000, 180_000],
+            ["k_render_step<1, 8, false>", 150_000, 250_000]]
+    _trace(str(tmp_path), rows)
+    out = bench.step_gaps(str(tmp_path), skip=0.0)
+    assert "busy 1.000 of it" in out
+    assert "total gap 0.0 ms" in out
+    # a gap after the latest end seen so far, not after the previous launch's
+    rows.append(["k_render_step<3, 8, false>", 300_000, 350_000])
+    _trace(str(tmp_path), rows)
+    out = bench.step_gaps(str(tmp_path), skip=0.0)
+    assert "mean gap 16.7 us" in out  # gaps 0, 0, 50 us over three intervals
+
+
+def _counters(path, counter, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for d, name, v in rows:
+            w.writerow([d, name, counter, v])
+
+
+def test_pmc_traffic_calibration(tmp_path):
+    neg = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(x)"
+    ren = "void fnr::k_render<0, 8, false>(fnr::RenderArgs)"
+    f, w = str(tmp_path / "fetch"), str(tmp_path / "write")
+    # the calibration kernel reads 1 GiB but FETCH_SIZE shows half of it
+    # (factor 2); counter rows split over two per-XCD records per dispatch
+    _counters(f, "FETCH_SIZE", [(1, neg, 262144.0), (1, neg, 262144.0), (2, neg, 524288.0),
+                                (3, ren, 1000.0), (3, ren, 500.0)])
+    _counters(w, "WRITE_SIZE", [(1, neg, 1048576.0), (2, ren, 200.0)])
+    out = bench.pmc_traffic(f, w)
+    assert out["fetch"]["calib_factor"] == pytest.approx(2.0)
+    assert out["fetch"]["kib_per_dispatch"] == pytest.approx(1500.0)
+    assert out["fetch"]["bytes"] == pytest.approx(1500.0 * 1024 * 2)
+    assert out["write"]["calib_factor"] == pytest.approx(1.0)
+    assert out["hbm_bytes_per_launch"] == round(1500 * 1024 * 2 + 200 * 1024)
+    # missing calibration kernel: refused
+    _counters(w, "WRITE_SIZE", [(2, ren, 200.0)])
+    with pytest.raises(SystemExit):
+        bench.pmc_traffic(f, w)
