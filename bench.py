@@ -882,6 +882,15 @@ def main():
                         "brick_sparse": storage_of(st)[1]}
         if not args.no_cpu and st != "f32":
             variants[st].update({k2: round(v2, 6) for k2, v2 in psnr_in[st].items()})
+        if units is not None and st in caches:
+            # the FP32 cache's sample counts with this format's record payload
+            # over this format's launch time
+            _, pl = caches[st].record_bytes
+            vbytes = (units["occ_samples"] * pl + units["hit_rays"] * 4 * spec.D * 4 +
+                      units["rays"] * 16) * nv
+            gbs = vbytes / (float(np.mean(r["step_ms"])) / 1e3) / 1e9
+            variants[st].update({"record_payload_bytes": pl, "alg_gb_per_s": round(gbs, 1),
+                                 "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
     line["variants"] = variants
     if not args.no_extras:
         if "f16" in caches and "fp8" in caches:
