@@ -150,19 +150,49 @@ def time_batched(fn, cache, views, N, eps, steps, warmup):
     return wall, np.array([a.elapsed_time(b) for a, b in evs]), outs
 
 
-def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs, seed=11):
-    """The FP64 oracle, single-threaded, on random pixels of every view (stops
-    at the time budget after completing a whole view). Each view's oracle
-    result is compared at once with the GPU renders in ``outs`` (storage ->
-    list of [H,W,4] device tensors) and only the summary is kept."""
+def host_cpu():
+    """CPU model name and logical CPU counts of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(cpu_model=model, nproc=os.cpu_count(), usable_cpus=usable)
+
+
+def oracle_threads():
+    """Threads of the all-core oracle leg: the CPUs this process may use,
+    capped by OMP_NUM_THREADS when it is set (the host's share of CPUs)."""
+    n = host_cpu()["usable_cpus"] or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs, seed=11,
+                  threads=1):
+    """The FP64 oracle on random pixels of every view, single-threaded (stops
+    at the time budget after completing a whole view) and, on the same pixels,
+    split into row bands over `threads` threads (bitwise the same results,
+    checked). Each view's oracle result is compared at once with the GPU
+    renders in ``outs`` (storage -> list of [H,W,4] device tensors) and only
+    the summary is kept."""
     import oracle
     import torch
     sb, slot, ss, su = sparse
     sc = oracle.Scene(beta, k=spec.k, sparse=(sb, slot, ss, su), in_box=True, occ_brick=8)
     rng = np.random.default_rng(seed)
-    rays, t_cpu, nviews = 0, 0.0, 0
+    rays, t_cpu, t_mt, nviews = 0, 0.0, 0.0, 0
     totals = dict(hit=0, occ_samples=0, rays=0, pixels=0)
-    f32 = dict(worst=0.0, fails=0, checked=0)
+    f32 = dict(worst=0.0, fails=0, checked=0, unchecked=0)
     other = {st: dict(worst=0.0, se=0.0, n=0) for st in outs if st != "f32"}
     for vi, v in enumerate(views):
         pix = np.sort(rng.choice(v.H * v.W, pix_per_view, replace=False))
@@ -170,6 +200,14 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs
         r = oracle.render(sc, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, pix=pix,
                           tol=oracle.DEFAULT_TOL)
         t_cpu += time.perf_counter() - t0
+        if threads > 1:
+            t0 = time.perf_counter()
+            rm = oracle.render(sc, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, pix=pix,
+                               tol=oracle.DEFAULT_TOL, threads=threads)
+            t_mt += time.perf_counter() - t0
+            if not (np.array_equal(rm["rgba"], r["rgba"]) and rm["counts"] == r["counts"]):
+                raise RuntimeError("threaded oracle differs from the single-threaded one")
+            del rm
         rays += len(pix)
         nviews += 1
         for key in ("hit", "occ_samples", "rays"):
@@ -181,6 +219,7 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs
         unchecked = (r["flags"] & oracle.UNCHECKED) != 0
         f32["fails"] += int((~ok & ~unchecked).sum())
         f32["checked"] += int((~unchecked).sum())
+        f32["unchecked"] += int(unchecked.sum())
         if (~unchecked).any():
             f32["worst"] = max(f32["worst"], float(err[~unchecked].max()))
         # the other formats over the same checked pixels (an unchecked pixel
@@ -193,12 +232,32 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs
             rc = {key: r[key][chk] for key in ("cand", "ncand")}
             err, _ = oracle.matches(g, rc, 1.0)
             acc["worst"] = max(acc["worst"], float(err.max()))
-            acc["se"] += float(np.sum((g[:, :3] - r["rgba"][chk][:, :3]) ** 2))
+            acc["se"] += float(np.sum((g[:, :3] - oracle.matched(g, rc)[:, :3]) ** 2))
             acc["n"] += g.shape[0] * 3
         del r
         if t_cpu >= seconds:
             break
-    return rays, t_cpu, nviews, totals, f32, other
+    return dict(rays=rays, t_cpu=t_cpu, t_mt=t_mt, threads=threads, nviews=nviews,
+                totals=totals, f32=f32, other=other)
+
+
+def launch_units(totals, views):
+    """Per-launch counts behind the algorithmic bytes: the oracle's per-ray
+    averages over its sampled pixels times the rays of the whole launch."""
+    rays = float(sum(v.H * v.W for v in views))
+    per_ray = rays / totals["rays"]
+    return dict(rays=rays, occ_samples=totals["occ_samples"] * per_ray,
+                hit_rays=totals["hit"] * per_ray)
+
+
+def alg_bytes(units, payload, D):
+    """Algorithmic bytes of a launch: the record payload of every sample in an
+    occupied brick, the four direction cells (D floats each) per hit ray, the
+    16-byte RGBA write per pixel."""
+    rec = units["occ_samples"] * payload
+    beta = units["hit_rays"] * 4 * D * 4
+    wr = units["rays"] * 16
+    return dict(records=rec, beta=beta, writes=wr, total=rec + beta + wr)
 
 
 def time_launches(fn_launch, reps, warmup):
@@ -250,17 +309,19 @@ def precision_sweep(fn, reps=20):
             for v, o in zip(views, outs):
                 fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps, out=o)
         ms = time_launches(orbit, reps, 3)
-        errs, se, n, se_hit, n_hit = [], 0.0, 0, 0.0, 0
+        errs, se, n, se_hit, n_hit, se_p = [], 0.0, 0, 0.0, 0, 0.0
         for o, res in zip(outs, ref):
             g = o.reshape(-1, 4).cpu().numpy().astype(np.float64)
-            # max-abs against the nearest admissible oracle result (voxel-face
-            # and stop-point ties); PSNR against the oracle's primary result
+            # max-abs and PSNR against the nearest admissible oracle result
+            # (voxel-face and stop-point ties); PSNR against the oracle's
+            # primary result beside it
             err, _ = oracle.matches(g, res, 1.0)
             errs.append(float(err.max()))
-            r = res["rgba"]
+            r = oracle.matched(g, res)
             d2 = (g[:, :3] - r[:, :3]) ** 2
             se += d2.sum()
             n += d2.size
+            se_p += float(((g[:, :3] - res["rgba"][:, :3]) ** 2).sum())
             hit = r[:, 3] > 0.01
             se_hit += d2[hit].sum()
             n_hit += d2[hit].size
@@ -269,6 +330,7 @@ def precision_sweep(fn, reps=20):
         psnr = lambda e, m: float("inf") if e == 0 else 10 * np.log10(m / e)
         out[st] = {"max_abs_err": float(max(errs)), "psnr_db": round(psnr(se, n), 3),
                    "psnr_hit_db": round(psnr(se_hit, n_hit), 3),
+                   "psnr_vs_primary_db": round(psnr(se_p, n), 3),
                    "mrays_per_s": round(rays / (float(np.mean(ms)) / 1e3) / 1e6, 1),
                    "alg_gb_per_s": round(alg / (float(np.mean(ms)) / 1e3) / 1e9, 1)}
         cache.destroy()
@@ -390,13 +452,15 @@ def bake_measure(fn, k=768, l=384, slab=64, sample=3000, cpu_points=1 << 18, wit
     return out
 
 
-def voxel_sweep(fn, main=None, ks=(256, 384, 512, 768), nviews=8, reps=3, pix=200):
+def voxel_sweep(fn, main=None, ks=(256, 384, 512, 768, 1024), nviews=8, reps=3, pix=200,
+                sparse_from=1024):
     """The per-voxel integration (N = 0: every voxel a ray crosses) against N=192
     samples in the box, on the paper-scale generator at several k (seed 1,
-    FP32 caches), the first nviews views of the 800x800 orbit in one launch
-    each; sampled pixels of one view against the oracle's traversal. main =
-    (k, FP32 cache, brick-sparse copy or None, beta) of the scene already
-    built, reused at its k."""
+    FP32 caches; brick-sparse from k = sparse_from on, so that k = 1024 fits
+    beside the caches already resident), the first nviews views of the
+    800x800 orbit in one launch each; sampled pixels of one view against the
+    oracle's traversal. main = (k, FP32 cache, brick-sparse copy or None, beta)
+    of the scene already built, reused at its k."""
     import oracle
     import synth
     import torch
@@ -409,9 +473,10 @@ def voxel_sweep(fn, main=None, ks=(256, 384, 512, 768), nviews=8, reps=3, pix=20
             _, cache, sparse, beta = main
             own = False
         else:
-            p_, beta, cs, sparse, _ = build_caches(spec, ["f32"], True, "cuda")
-            cache, own = cs["f32"], True
-        row = {}
+            st = "f32s" if k >= sparse_from else "f32"
+            p_, beta, cs, sparse, _ = build_caches(spec, [st], True, "cuda")
+            cache, own = cs[st], True
+        row = {"cache": "brick-sparse FP32" if own and k >= sparse_from else "dense FP32"}
         for name, N in (("voxels", 0), ("n192", 192)):
             outs = [torch.empty((v.H, v.W, 4), dtype=torch.float32, device="cuda") for v in views]
             ms = time_launches(lambda: fn.render_batch(cache, views, N, 1e-4, outs=outs), reps, 1)
@@ -633,10 +698,12 @@ def counter_means(root, counter):
     return {name: tot / max(1, len(ids)) for name, (tot, ids) in acc.items()}
 
 
-def pmc_traffic(fetch_dir, write_dir, kernel="k_render<0, 8, false>", calib="neg_kernel"):
+def pmc_traffic(fetch_dir, write_dir, tcc_dir=None, kernel="k_render<0, 8, false>",
+                calib="neg_kernel"):
     """HBM bytes per launch of the render kernel from FETCH_SIZE and WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
-    calibration kernel (torch.neg over 2^28 floats: 1 GiB read, 1 GiB written)."""
+    calibration kernel (torch.neg over 2^28 floats: 1 GiB read, 1 GiB written);
+    with a TCC_HIT_sum / TCC_MISS_sum run, also the kernel's L2 hit rate."""
     out = {}
     for key, root, cn in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         m = counter_means(root, cn)
@@ -648,9 +715,16 @@ def pmc_traffic(fetch_dir, write_dir, kernel="k_render<0, 8, false>", calib="neg
         factor = (1 << 30) / (kc[0] * 1024.0)
         out[key] = dict(kib_per_dispatch=kr[0], calib_kib_per_dispatch=kc[0],
                         calib_factor=factor, bytes=kr[0] * 1024.0 * factor)
-    return {"kernel": kernel, "kernel_digest": kernel_digest(),
-            "hbm_bytes_per_launch": round(out["fetch"]["bytes"] + out["write"]["bytes"]),
-            "fetch": out["fetch"], "write": out["write"]}
+    res = {"kernel": kernel, "kernel_digest": kernel_digest(),
+           "hbm_bytes_per_launch": round(out["fetch"]["bytes"] + out["write"]["bytes"]),
+           "fetch": out["fetch"], "write": out["write"]}
+    if tcc_dir:
+        hit = [v for n, v in counter_means(tcc_dir, "TCC_HIT_sum").items() if kernel in n]
+        miss = [v for n, v in counter_means(tcc_dir, "TCC_MISS_sum").items() if kernel in n]
+        if len(hit) == 1 and len(miss) == 1:
+            res["tcc_hit"], res["tcc_miss"] = hit[0], miss[0]
+            res["l2_hit_rate"] = round(hit[0] / (hit[0] + miss[0]), 4)
+    return res
 
 
 def main():
@@ -685,9 +759,14 @@ def main():
                     help="skip the precision sweep, the batched launch and the serving sample")
     ap.add_argument("--step-gaps", metavar="DIR",
                     help="busy fraction and gaps of the serving step kernels in a kernel trace")
-    ap.add_argument("--pmc-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+    ap.add_argument("--pmc-traffic", nargs="+", metavar="DIR",
                     help="print the render kernel's calibrated HBM bytes per launch (JSON) "
-                         "from FETCH_SIZE and WRITE_SIZE runs made with --calibrate-copy")
+                         "from FETCH_SIZE and WRITE_SIZE runs made with --calibrate-copy "
+                         "(FETCH_DIR WRITE_DIR [TCC_DIR]; the third adds the L2 hit rate)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "refill", "wide"],
+                    help="schedule of the render launches (fastnerf_set_schedule)")
+    ap.add_argument("--pmc-kernel", default="k_render<0, 8, false>",
+                    help="kernel name (substring) that --pmc-traffic reports")
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile))
@@ -696,7 +775,9 @@ def main():
         print(step_gaps(args.step_gaps))
         return
     if args.pmc_traffic:
-        print(json.dumps(pmc_traffic(*args.pmc_traffic), indent=1))
+        if len(args.pmc_traffic) not in (2, 3):
+            raise SystemExit("--pmc-traffic takes FETCH_DIR WRITE_DIR [TCC_DIR]")
+        print(json.dumps(pmc_traffic(*args.pmc_traffic, kernel=args.pmc_kernel), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the renderer "
@@ -709,6 +790,7 @@ def main():
     import synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fn.lib()
+    fn.set_schedule(args.schedule)
 
     if args.serving:
         t0 = time.perf_counter()
@@ -824,49 +906,63 @@ def main():
     if not args.no_cpu:
         outs_all = {"f32": outs_f32}
         outs_all.update({st: results[st]["outs"] for st in storages if st != "f32"})
-        rays, t_cpu, nv, totals, f32, other = oracle_sample(
-            beta, sparse, spec, views, N, eps, args.cpu_pixels, args.cpu_seconds, outs_all)
-        line["cpu_baseline"] = {
-            "value": round(rays / t_cpu / 1e6, 5), "unit": "Mrays/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"{rays} random pixels ({args.cpu_pixels} per view over the first "
-                       f"{nv} views) of the same workload, FP64 single-threaded, "
-                       f"{t_cpu:.1f} s"),
-        }
-        # algorithmic bytes per launch: records of samples in occupied bricks,
-        # the four direction cells per hit ray, the RGBA write (sampled counts
-        # scaled to whole views)
-        scale = totals["pixels"] / totals["rays"] / nv
-        units = dict(occ_samples=totals["occ_samples"] * scale, hit_rays=totals["hit"] * scale,
-                     rays=totals["pixels"] / nv)
+        threads = oracle_threads()
+        o = oracle_sample(beta, sparse, spec, views, N, eps, args.cpu_pixels, args.cpu_seconds,
+                          outs_all, threads=threads)
+        host = host_cpu()
+        sample = (f"{o['rays']} random pixels ({args.cpu_pixels} per view over the first "
+                  f"{o['nviews']} of the {nv} views) of the same workload, FP64")
+        one = dict(value=round(o["rays"] / o["t_cpu"] / 1e6, 5), unit="Mrays/s", cores=1,
+                   seconds=round(o["t_cpu"], 2))
+        if threads > 1:
+            line["cpu_baseline"] = {
+                "value": round(o["rays"] / o["t_mt"] / 1e6, 5), "unit": "Mrays/s",
+                "cores": threads, "kind": "oracle",
+                "sample": sample + f", split into row bands over {threads} threads "
+                                   f"({o['t_mt']:.1f} s; bitwise equal to the 1-thread run)",
+                "single_core": one, **host}
+        else:
+            line["cpu_baseline"] = {**one, "kind": "oracle", "sample": sample + ", 1 thread",
+                                    **host}
+        units = launch_units(o["totals"], views)
+        f32 = o["f32"]
         line["parity"] = {"pixels": f32["checked"], "max_abs_err": f32["worst"],
-                          "failing": f32["fails"], "tol": 1e-4,
+                          "failing": f32["fails"], "unchecked": f32["unchecked"], "tol": 1e-4,
                           "reference": "FP64 oracle, FP32 cache"}
-        for st, acc in other.items():
+        for st, acc in o["other"].items():
             m = acc["se"] / max(1, acc["n"])
             psnr_in[st] = dict(max_abs_err=acc["worst"],
                                psnr_db=(float("inf") if m == 0 else 10 * np.log10(1 / m)))
     # ---------------------------------------------------------------- roofline
     if units is not None:
         stride, payload = caches["f32"].record_bytes
-        D = spec.D
-        alg_bytes = units["occ_samples"] * payload + units["hit_rays"] * 4 * D * 4 + \
-            units["rays"] * 16
-        alg_bytes *= nv  # the launch renders every view of the step
+        ab = alg_bytes(units, payload, spec.D)
         avg_s = float(np.mean(r32["step_ms"])) / 1e3
-        achieved = alg_bytes / avg_s / 1e9
-        traffic = None
+        achieved = ab["total"] / avg_s / 1e9
+        pmc = None
         if os.path.exists(PMC_SUMMARY):
             pmc = json.load(open(PMC_SUMMARY))
-            if pmc.get("kernel_digest") == kernel_digest():
-                traffic = pmc.get("hbm_bytes_per_launch")
-        line["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1),
-                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                            "kernel": f"k_render<FP32, D<=8, nearest>, {nv} views per launch",
-                            "algorithmic_bytes_per_launch": round(alg_bytes),
-                            "occupied_samples_per_launch": round(units["occ_samples"]),
-                            "record_payload_bytes": payload, "record_stride_bytes": stride}
+            if pmc.get("kernel_digest") != kernel_digest():
+                pmc = None
+        traffic = pmc.get("hbm_bytes_per_launch") if pmc else None
+        line["roofline"] = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"k_render<FP32, D<=8, nearest>, {nv} views per launch",
+            "algorithmic_bytes_per_launch": round(ab["total"]),
+            "bytes_per_launch": {key: round(ab[key]) for key in ("records", "beta", "writes")},
+            "frac_records_and_writes": round((ab["records"] + ab["writes"]) / avg_s / 1e9 /
+                                             HBM_PEAK_GBS, 4),
+            "occupied_samples_per_launch": round(units["occ_samples"]),
+            "hit_rays_per_launch": round(units["hit_rays"]),
+            "rays_per_launch": round(units["rays"]),
+            "record_payload_bytes": payload, "record_stride_bytes": stride,
+            "launch_ms_mean": round(avg_s * 1e3, 4),
+            "l2_hit_rate": pmc.get("l2_hit_rate") if pmc else None,
+            "useful_bytes_fraction": (round(ab["total"] / traffic, 4) if traffic else None),
+            "note": ("achieved = algorithmic bytes per launch / mean launch time (HIP events on "
+                     "the launch stream); traffic, L2 hit rate from rocprofv3 counters of the "
+                     "same kernel source (null when the source changed since)")}
     variants = {}
     for st in storages:
         r = results[st]
@@ -886,13 +982,55 @@ def main():
             # the FP32 cache's sample counts with this format's record payload
             # over this format's launch time
             _, pl = caches[st].record_bytes
-            vbytes = (units["occ_samples"] * pl + units["hit_rays"] * 4 * spec.D * 4 +
-                      units["rays"] * 16) * nv
-            gbs = vbytes / (float(np.mean(r["step_ms"])) / 1e3) / 1e9
+            vb = alg_bytes(units, pl, spec.D)
+            sec = float(np.mean(r["step_ms"])) / 1e3
+            gbs = vb["total"] / sec / 1e9
             variants[st].update({"record_payload_bytes": pl, "alg_gb_per_s": round(gbs, 1),
-                                 "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+                                 "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                 "hbm_frac_records_and_writes": round(
+                                     (vb["records"] + vb["writes"]) / sec / 1e9 /
+                                     HBM_PEAK_GBS, 4)})
     line["variants"] = variants
+    if not args.no_extras and not args.no_single:
+        # the a9 mechanism: the same FP32 launches with one tile per wave
+        fn.set_schedule("tiles")
+        wall_t, step_t, _ = time_batched(fn, caches["f32"], views, N, eps, args.steps,
+                                         args.warmup)
+        frame_t = time_single(fn, caches["f32"], views, N, eps, 2, 1)
+        fn.set_schedule(args.schedule)
+        line["schedule_compare"] = {
+            "note": "FP32 cache; refill = wave-level ray queue (ballot, LDS pool, refill), "
+                    "tiles = one 8x8 tile per wave until its slowest ray stops",
+            "schedule": args.schedule,
+            "default": {
+                "launch_ms_mean": round(float(np.mean(r32["step_ms"])), 4),
+                "single_view_frame_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
+                "single_view_frame_ms_p99": round(float(np.percentile(frame_ms, 99)), 4)},
+            "tiles": {"launch_ms_mean": round(float(np.mean(step_t)), 4),
+                      "single_view_frame_ms_p50": round(float(np.percentile(frame_t, 50)), 4),
+                      "single_view_frame_ms_p99": round(float(np.percentile(frame_t, 99)), 4)}}
+        log(f"schedules: {line['schedule_compare']}")
     if not args.no_extras:
+        # the served path per storage format on one resident copy of the same
+        # scene: latency at 200 requests/s and throughput when saturated
+        by_fmt = {}
+        for st in ("f32", "f16", "fp8"):
+            if st not in caches:
+                continue
+            lo = serve_poisson(fn, [caches[st]], 200, 300, 30)
+            hi = serve_poisson(fn, [caches[st]], 12800, 800, 80)
+            by_fmt[st] = {"p50_ms_at_200": lo["latency_ms_p50"],
+                          "p99_ms_at_200": lo["latency_ms_p99"],
+                          "saturated_frames_per_s": hi["frames_per_s"],
+                          "saturated_mrays_per_s": hi["mrays_per_s"],
+                          "psnr_db_vs_fp64_oracle": (None if st == "f32" or st not in psnr_in
+                                                     else round(psnr_in[st]["psnr_db"], 2))}
+        if "f32" in by_fmt:
+            for st, r in by_fmt.items():
+                r["saturated_speedup_vs_f32"] = round(
+                    r["saturated_frames_per_s"] / by_fmt["f32"]["saturated_frames_per_s"], 3)
+        line["serving_by_format"] = by_fmt
+        log(f"serving by format: {by_fmt}")
         if "f16" in caches and "fp8" in caches:
             # continuous batching over the two reduced-precision caches already resident
             r = serve_poisson(fn, [caches["f16"], caches["fp8"]], 200, 300, 30)

@@ -153,11 +153,41 @@ fastnerf_status fastnerf_render(fastnerf_cache cache, const float K[9], const fl
 
 /* Renders nviews views of one cache in a single persistent launch. K, c2w,
  * H, W, near, far and out are host arrays of nviews entries (out[i] is a
- * device buffer of H[i]*W[i]*4 floats). N as for fastnerf_render. */
+ * device buffer of H[i]*W[i]*4 floats). N as for fastnerf_render. The view
+ * descriptors are staged through a ring of 8 pinned buffers per stream, so
+ * the call returns without waiting for earlier launches; only a ninth batch
+ * enqueued while the eighth-previous one's descriptor copy has not yet run on
+ * the stream waits for that copy. Calls on one stream from several host
+ * threads are serialised by the library. [Sec. 3.1 Eq. 1, Sec. 4] */
 fastnerf_status fastnerf_render_batch(fastnerf_cache cache, int32_t nviews, const float *K,
                                       const float *c2w, const int32_t *H, const int32_t *W,
                                       const float *near, const float *far, int32_t N, float eps,
                                       float *const *out, hipStream_t stream);
+
+/* Scheduling of the fixed-N render launches (fastnerf_render,
+ * fastnerf_render_batch), process-wide. TILES: each
+ * wave renders one 8x8 pixel tile at a time (one ray per lane) and takes the
+ * next tile when all of its rays have stopped. REFILL: the wave-level ray
+ * queue -- after each window of samples the wave takes a ballot of its live
+ * lanes and, once enough have retired, refills them with set-up rays from a
+ * per-wave pool in LDS, replenished a tile at a time (the rays of a tile that
+ * miss the box are written at once, the others compacted into the pool).
+ * WIDE: tiles with more records in flight per lane at fewer waves per SIMD,
+ * which shortens the heaviest rays' dependency chains in launches too small
+ * to fill the chip. AUTO (the default): WIDE for launches of at most 20,000
+ * tiles (about two 800x800 views), TILES otherwise. Every schedule gives
+ * bitwise the same image:
+ * each ray is computed by one lane with the same arithmetic. Serving steps
+ * and voxel traversal (N = 0) use TILES. Returns EINVAL for an unknown
+ * value. */
+enum {
+  FASTNERF_SCHEDULE_AUTO = 0,
+  FASTNERF_SCHEDULE_TILES = 1,
+  FASTNERF_SCHEDULE_REFILL = 2,
+  FASTNERF_SCHEDULE_WIDE = 3
+};
+fastnerf_status fastnerf_set_schedule(int32_t schedule);
+int32_t fastnerf_get_schedule(void);
 
 /* Test hook: the kernel's own lookups. pts and dirs are device arrays of n
  * points / unit directions (3 floats each); sigma_u receives n*(1+3D) floats
@@ -268,9 +298,9 @@ fastnerf_status fastnerf_mlp_destroy(fastnerf_mlp mlp);
 /* ------------------------------------------------ direction filtering and LOD */
 
 /* Smooths a direction-cache table beta[l][l][D] (theta row, phi column) with
- * a Gaussian of standard deviation `sigma` cells on each axis (Sec. 4: the
- * direction cache can be processed with a Gaussian or other kernel to smooth
- * directional effects): out[j][m] = sum_{a,b} g(a) g(b) in[clamp(j+a)][(m+b)
+ * a Gaussian of standard deviation `sigma` cells on each axis (Sec. 4 allows
+ * smoothing the direction cache with a filter kernel, a Gaussian for one, to
+ * soften view-dependent effects): out[j][m] = sum_{a,b} g(a) g(b) in[clamp(j+a)][(m+b)
  * mod l] with g(t) = exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma),
  * normalised to sum 1 -- periodic in phi, the edge rows repeated in theta
  * (the lookup clamps theta the same way). Convex combinations stay convex, so

@@ -25,18 +25,18 @@ MAXCAND = 32
 HIT, AMBIG, UNCHECKED = 1, 2, 4
 
 # Default admissibility bands (reading R13): a sample within 1e-3 voxel of a
-# cell boundary may take either voxel (FP32 grid coordinates of the kernel are
-# good to about 3e-4 voxel at k = 768); a stop point within 1e-3 of ln(1/eps)
+# voxel face (but not on it) may take either voxel (FP32 grid coordinates are
+# good to about 1.3e-4 voxel at k = 768); a stop point within 1e-3 of ln(1/eps)
 # in optical depth may be taken or not; nearest direction cells within 1e-5 rad.
 DEFAULT_TOL = (1e-3, 1e-5, 1e-3)
-TIE = 1.0 / 512.0  # cell boundaries sit this many voxels below the faces (reading R6b)
+ON_FACE = 1e-9  # a grid coordinate this close to a face lies on it (reading R6b)
 
 
 def build(verbose: bool = False) -> str:
     """Compiles the oracle with gcc (strict IEEE double, no contraction)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-o", LIB_PATH + ".tmp", os.path.join(_HERE, "fastnerf_oracle.c"),
-           "-lm"]
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-pthread",
+           "-ffp-contract=off", "-fno-fast-math", "-o", LIB_PATH + ".tmp",
+           os.path.join(_HERE, "fastnerf_oracle.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -89,6 +89,8 @@ def lib():
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, P(_Counts)]
         L.orc_render.restype = ctypes.c_int
+        L.orc_render_mt.argtypes = L.orc_render.argtypes + [ctypes.c_int32]
+        L.orc_render_mt.restype = ctypes.c_int
         L.orc_pixel_ray.argtypes = [P(_View), ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_interval.argtypes = [P(_Scene), P(_View), dp, dp, dp, dp]
         L.orc_interval.restype = ctypes.c_int
@@ -189,10 +191,12 @@ def _tol(tol):
 
 
 def render(scene: Scene, K, c2w, H, W, near, far, N, eps, pix=None, tol=DEFAULT_TOL,
-           candidates=True):
+           candidates=True, threads=1):
     """Renders pixels (all when ``pix`` is None). Returns a dict with ``rgba``
     [n,4] (primary result), ``cand`` [n,MAXCAND,4] / ``ncand`` [n] (every
-    admissible result), ``flags`` [n] and ``counts`` (dict)."""
+    admissible result), ``flags`` [n] and ``counts`` (dict). ``threads`` > 1
+    splits the pixel list into that many contiguous bands, one thread each
+    (bitwise the same result)."""
     v = _view(K, c2w, H, W, near, far, N, eps)
     if pix is None:
         n, pp = H * W, None
@@ -205,9 +209,12 @@ def render(scene: Scene, K, c2w, H, W, near, far, N, eps, pix=None, tol=DEFAULT_
     flags = np.zeros(n, dtype=np.int32)
     cnt = _Counts()
     t = _tol(tol) if tol is not None else _tol((0.0, 0.0, 0.0))
-    rc = lib().orc_render(ctypes.byref(scene.struct), ctypes.byref(v), ctypes.byref(t), n,
-                          _ptr(pp), _ptr(rgba), _ptr(cand), _ptr(ncand), _ptr(flags),
-                          ctypes.byref(cnt))
+    args = (ctypes.byref(scene.struct), ctypes.byref(v), ctypes.byref(t), n, _ptr(pp),
+            _ptr(rgba), _ptr(cand), _ptr(ncand), _ptr(flags), ctypes.byref(cnt))
+    if threads > 1:
+        rc = lib().orc_render_mt(*args, int(threads))
+    else:
+        rc = lib().orc_render(*args)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     counts = {f: getattr(cnt, f) for f, _ in _Counts._fields_}
@@ -302,3 +309,13 @@ def matches(rgba_gpu, res, tol):
     mask = np.arange(cand.shape[1])[None, :] < ncand[:, None]
     err = np.where(mask, err, np.inf).min(axis=1)
     return err, err <= tol
+
+
+def matched(rgba_gpu, res):
+    """Per pixel, the admissible oracle result nearest (max-abs over RGBA) to
+    the given one: the result the pass protocol matches it with."""
+    g = np.asarray(rgba_gpu, dtype=np.float64).reshape(-1, 4)
+    cand, ncand = res["cand"], res["ncand"]
+    err = np.abs(cand - g[:, None, :]).max(axis=2)
+    err = np.where(np.arange(cand.shape[1])[None, :] < ncand[:, None], err, np.inf)
+    return cand[np.arange(len(g)), err.argmin(axis=1)]

@@ -3,9 +3,9 @@ choice -- TEST INFRASTRUCTURE ONLY (only the tests, ``__graft_entry__.smoke()``
 and the CPU-baseline leg of ``bench.py`` may import it; it shares no code with
 the HIP library).
 
-Readings (the paper only says that the direction cache can be processed with
-a Gaussian or other kernel, Sec. 4, and that caches of several resolutions act
-like levels of detail, Sec. 5):
+Readings (the paper only allows smoothing the direction cache with a filter
+kernel such as a Gaussian, Sec. 4, and compares caches of several resolutions
+to levels of detail, Sec. 5):
 
 * filter: a separable Gaussian over the table's cells with standard deviation
   sigma cells, taps |t| <= ceil(3 sigma) with weights exp(-t^2 / (2 sigma^2))

@@ -30,29 +30,30 @@
  *      is bilinear over cell centres, periodic in phi, clamped in theta.
  *   R5 theta is measured from +z, phi = atan2(y, x) in [0, 2pi).
  *   R6 position-cache values sit at cell centres; the nearest voxel of g is
- *      floor(g) (a point on a face goes to the upper cell, the far box face to
- *      the last cell); outside the box density is 0.
+ *      the cell that contains it, floor(g) (a point on a face goes to the upper
+ *      cell, the far box face to the last cell); outside the box density is 0.
  *   R7 trilinear lookups clamp corner indices to the grid inside the box.
  *   R8 termination: stop before sample i once T_i < eps, i.e. once the
  *      accumulated optical depth exceeds ln(1/eps); the background is then
  *      composited with the remaining transmittance.
  *   R9/R11 RGB includes the background times the final transmittance; A = 1 - T.
  *   R10 no activation is applied to the colour of Eq. 5.
- *   R13 a sample whose grid coordinate lies within gamma (voxels) of a cell
- *      boundary may take either neighbour, and a stop point within tau_band of ln(1/eps) may be
- *      taken or not: all such variants are admissible results (the FP32 kernel
- *      cannot resolve them), and they are enumerated.
- *   R6b ties: when the sample spacing is commensurate with the grid (k/N
- *      voxels per sample along an axis that the ray crosses from face to face,
- *      e.g. k = 768, N = 192) every sample lies exactly on a voxel face. A
- *      point on a face belongs to the upper cell (R6); so that rounding cannot
- *      flip that choice, the cell boundaries are taken 2^-9 voxel below the
- *      faces: the nearest voxel of grid coordinate g is min(floor(g + 2^-9),
- *      k - 1) inside the box.
+ *   R13 a sample whose grid coordinate lies within gamma (voxels) of a voxel
+ *      face may take either neighbour (except one on the face, R6b), and a stop
+ *      point within tau_band of ln(1/eps) may be taken or not: all such
+ *      variants are admissible results (the FP32 kernel cannot resolve them),
+ *      and they are enumerated.
+ *   R6b faces hit exactly: when the sample spacing is commensurate with the
+ *      grid (k/N voxels per sample along an axis that the ray crosses from
+ *      face to face, e.g. k = 768, N = 192) every sample lies on a voxel face.
+ *      R6 puts such a point in the upper cell; so that FP64 rounding of the
+ *      sample position cannot flip that choice, a grid coordinate within
+ *      ORC_ON_FACE (1e-9 voxel, far below any FP32 resolution) of a face counts
+ *      as lying on it. Everywhere else the nearest voxel is floor(g).
  *   R17 the transmittance sum of Eq. 1 runs over the samples before i.
  *   R18 voxel traversal (N = 0): the rendering procedure of Sec. 4 visits every
  *      voxel a ray crosses. The ray inside [near, far] intersected with the box
- *      is cut at every crossing of a cell boundary (the R6b boundaries); each
+ *      is cut at every crossing of a voxel face; each
  *      piece is one sample, of length delta_i equal to the piece's length and
  *      value that of the nearest voxel of its midpoint (nearest lookups only).
  *      The nearest-lookup field is constant on each piece, so this evaluates
@@ -62,6 +63,7 @@
 #include "fastnerf_oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -162,13 +164,15 @@ static double grid_coord(const orc_scene *s, int ax, double p) {
   return (p - s->bmin[ax]) * (double)s->k / (s->bmax[ax] - s->bmin[ax]);
 }
 
-/* Cell boundaries sit this far (in voxels) below the faces (reading R6b). */
-#define ORC_TIE (1.0 / 512.0)
+/* A grid coordinate this close (in voxels) to a face lies on it (reading R6b):
+   FP64 rounding of a sample position is about 1e-12 voxel at k <= 1024. */
+#define ORC_ON_FACE 1e-9
 
-/* Nearest voxel along one axis, -1 outside the box. */
+/* Nearest voxel along one axis (reading R6: the cell containing g, the upper
+   one on a face), -1 outside the box. */
 static int nn_coord(double g, int k) {
   if (g < 0.0 || g > (double)k) return -1;
-  int c = (int)floor(g + ORC_TIE);
+  int c = (int)floor(g + ORC_ON_FACE);
   return c > k - 1 ? k - 1 : c;
 }
 
@@ -326,8 +330,9 @@ static void work_free(ray_work *w) {
   free(w->dl);
 }
 
-/* Alternative nearest-voxel coordinate across the nearest cell boundary (or
-   box face), if the grid coordinate is within gamma voxels of it. */
+/* Alternative nearest-voxel coordinate across the nearest voxel face (or box
+   face), if the grid coordinate is within gamma voxels of it but not on it
+   (reading R13; a point on an interior face takes the upper cell, R6b). */
 static int nn_alternative(double g, int k, double gamma, int prim, int *alt) {
   if (fabs(g) < gamma) { /* lower box face */
     *alt = prim == -1 ? 0 : -1;
@@ -337,8 +342,10 @@ static int nn_alternative(double g, int k, double gamma, int prim, int *alt) {
     *alt = prim == -1 ? k - 1 : -1;
     return 1;
   }
-  double gt = g + ORC_TIE, n = floor(gt + 0.5);
-  if (n < 1.0 || n > (double)(k - 1) || fabs(gt - n) >= gamma || prim < 0) return 0;
+  double n = floor(g + 0.5);
+  if (n < 1.0 || n > (double)(k - 1) || fabs(g - n) >= gamma || fabs(g - n) <= ORC_ON_FACE ||
+      prim < 0)
+    return 0;
   *alt = prim == (int)n ? (int)n - 1 : (int)n;
   return *alt != prim;
 }
@@ -508,8 +515,8 @@ static int cmp_double(const void *a, const void *b) {
   return x < y ? -1 : (x > y);
 }
 
-/* Voxel traversal (R18): cuts [t0, t1] at every crossing of an interior cell
-   boundary (grid coordinate i - ORC_TIE, R6b) and makes each piece of positive
+/* Voxel traversal (R18): cuts [t0, t1] at every crossing of an interior voxel
+   face (grid coordinate i) and makes each piece of positive
    length a sample at its midpoint, with the nearest voxel of the midpoint and
    the piece's length. ts holds 3(k+1)+2 doubles. */
 static void place_segments(const orc_scene *s, const double o[3], const double d[3], double t0,
@@ -520,7 +527,7 @@ static void place_segments(const orc_scene *s, const double o[3], const double d
     if (d[ax] == 0.0) continue;
     double h = (s->bmax[ax] - s->bmin[ax]) / k;
     for (int i = 1; i < k; i++) {
-      double t = (s->bmin[ax] + (i - ORC_TIE) * h - o[ax]) / d[ax];
+      double t = (s->bmin[ax] + i * h - o[ax]) / d[ax];
       if (t > t0 && t < t1) ts[n++] = t;
     }
   }
@@ -679,6 +686,83 @@ int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_
   free(ts);
   work_free(&w);
   return 0;
+}
+
+/* The same render split into contiguous bands of the pixel list (row bands
+   when the list is in row order), one thread per band. Pixels are independent,
+   so the result is bitwise that of orc_render; the counts are summed. */
+typedef struct {
+  const orc_scene *s;
+  const orc_view *v;
+  const orc_tol *tol;
+  int64_t n;
+  int64_t *pix; /* the band's pixel ids */
+  double *rgba, *cand;
+  int32_t *ncand, *flags;
+  orc_counts counts;
+  int rc;
+} orc_band;
+
+static void *band_main(void *arg) {
+  orc_band *b = arg;
+  b->rc = orc_render(b->s, b->v, b->tol, b->n, b->pix, b->rgba, b->cand, b->ncand, b->flags,
+                     &b->counts);
+  return NULL;
+}
+
+int orc_render_mt(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_t npix,
+                  const int64_t *pix, double *rgba, double *cand, int32_t *ncand,
+                  int32_t *flags, orc_counts *counts, int32_t nthreads) {
+  if (nthreads < 1 || npix < 0 || !v) return -1;
+  if ((int64_t)nthreads > npix) nthreads = npix > 0 ? (int32_t)npix : 1;
+  orc_band *bands = calloc((size_t)nthreads, sizeof *bands);
+  pthread_t *th = calloc((size_t)nthreads, sizeof *th);
+  int64_t *ids = malloc(sizeof(int64_t) * (size_t)(npix > 0 ? npix : 1));
+  int rc = 0;
+  if (!bands || !th || !ids) {
+    free(bands);
+    free(th);
+    free(ids);
+    return -1;
+  }
+  for (int64_t q = 0; q < npix; q++) ids[q] = pix ? pix[q] : q;
+  int started = 0;
+  for (int b = 0; b < nthreads; b++) {
+    int64_t lo = npix * b / nthreads, hi = npix * (b + 1) / nthreads;
+    orc_band *B = &bands[b];
+    B->s = s;
+    B->v = v;
+    B->tol = tol;
+    B->n = hi - lo;
+    B->pix = ids + lo;
+    B->rgba = rgba ? rgba + 4 * lo : NULL;
+    B->cand = cand ? cand + lo * ORC_MAXCAND * 4 : NULL;
+    B->ncand = ncand ? ncand + lo : NULL;
+    B->flags = flags ? flags + lo : NULL;
+    if (pthread_create(&th[b], NULL, band_main, B) != 0) {
+      rc = -1;
+      break;
+    }
+    started++;
+  }
+  for (int b = 0; b < started; b++) pthread_join(th[b], NULL);
+  if (counts) memset(counts, 0, sizeof *counts);
+  for (int b = 0; b < started; b++) {
+    if (bands[b].rc != 0) rc = -1;
+    if (counts) {
+      counts->rays += bands[b].counts.rays;
+      counts->hit += bands[b].counts.hit;
+      counts->samples += bands[b].counts.samples;
+      counts->occ_samples += bands[b].counts.occ_samples;
+      counts->nonzero_samples += bands[b].counts.nonzero_samples;
+      counts->ambiguous_pixels += bands[b].counts.ambiguous_pixels;
+      counts->unchecked_pixels += bands[b].counts.unchecked_pixels;
+    }
+  }
+  free(bands);
+  free(th);
+  free(ids);
+  return rc;
 }
 
 int orc_trace(const orc_scene *s, const orc_view *v, int32_t x, int32_t y, double *t,

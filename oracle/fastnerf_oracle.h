@@ -81,6 +81,12 @@ int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_
                const int64_t *pix, double *rgba, double *cand, int32_t *ncand,
                int32_t *flags, orc_counts *counts);
 
+/* orc_render split into nthreads contiguous bands of the pixel list, one
+   thread each; bitwise the same results, counts summed. */
+int orc_render_mt(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_t npix,
+                  const int64_t *pix, double *rgba, double *cand, int32_t *ncand,
+                  int32_t *flags, orc_counts *counts, int32_t nthreads);
+
 /* Pieces of the definition, exposed for the pins. */
 void orc_pixel_ray(const orc_view *v, double x, double y, double o[3], double d[3]);
 int orc_interval(const orc_scene *s, const orc_view *v, const double o[3], const double d[3],

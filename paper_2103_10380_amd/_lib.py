@@ -66,6 +66,8 @@ SYMBOLS = {
     "fastnerf_render": (_i32, [_vp, _pf, _pf, _i32, _i32, _f32, _f32, _i32, _f32, _vp, _vp]),
     "fastnerf_render_batch": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _vp,
                                      _vp]),
+    "fastnerf_set_schedule": (_i32, [_i32]),
+    "fastnerf_get_schedule": (_i32, []),
     "fastnerf_debug_lookup": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fastnerf_model_bytes": (_dbl, [_dbl, _i64, _i64, _i32, _dbl, _dbl, _dbl]),
     "fastnerf_server_create": (_i32, [_vp, _i32, _u64, _i32, _vp]),
@@ -270,6 +272,21 @@ def render_batch(cache: Cache, views, N, eps, outs=None, stream=None):
     check(lib().fastnerf_render_batch(cache.handle, n, _ptr(K), _ptr(C), _ptr(H), _ptr(W),
                                       _ptr(nr), _ptr(fr), N, eps, ptrs, _stream(stream)))
     return outs
+
+
+SCHEDULES = {"auto": 0, "tiles": 1, "refill": 2, "wide": 3}
+
+
+def set_schedule(name: str):
+    """Process-wide schedule of fixed-N render launches: "auto", "tiles",
+    "refill" or "wide" (see fastnerf_set_schedule)."""
+    if name not in SCHEDULES:
+        raise ValueError(f"unknown schedule {name!r}")
+    check(lib().fastnerf_set_schedule(SCHEDULES[name]))
+
+
+def get_schedule() -> str:
+    return {v: k for k, v in SCHEDULES.items()}[lib().fastnerf_get_schedule()]
 
 
 def debug_lookup(cache: Cache, pts=None, dirs=None, stream=None):

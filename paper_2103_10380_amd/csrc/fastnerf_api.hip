@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -75,13 +76,25 @@ static bool finite_all(const float *v, int n) {
 }
 
 // Per (device, stream) launch state: the self-resetting tile-queue counters and
-// a staging area for batched view descriptors. Allocated once per stream.
-struct StreamState {
-  unsigned *counter = nullptr;
-  DevView *views = nullptr;
+// a ring of staging slots for batched view descriptors. A batch writes its
+// descriptors into the next slot's pinned buffer and copies them to the slot's
+// device buffer on the stream; the host waits only if that slot's previous copy
+// (kStageRing batches back) has not run yet, so batches enqueue without waiting
+// for earlier launches. Allocated once per stream.
+constexpr int kStageRing = 8;
+
+struct StageSlot {
+  DevView *views = nullptr;       // device
   DevView *views_host = nullptr;  // pinned
   int cap = 0;
-  hipEvent_t staged = nullptr;    // last descriptor copy out of views_host
+  hipEvent_t copied = nullptr;    // recorded after the slot's last descriptor copy
+};
+
+struct StreamState {
+  unsigned *counter = nullptr;
+  StageSlot slot[kStageRing];
+  int next = 0;                   // ring position of the next batch
+  std::mutex mu;                  // held while a batch takes and fills its slot
 };
 
 static std::mutex g_streams_mu;
@@ -100,7 +113,8 @@ fastnerf_status stream_state(hipStream_t s, StreamState **out) {
   StreamState *st = new StreamState();
   hipError_t e = hipMalloc(&st->counter, kQueueCounters * sizeof(unsigned));
   if (e == hipSuccess) e = hipMemset(st->counter, 0, kQueueCounters * sizeof(unsigned));
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->staged, hipEventDisableTiming);
+  for (int q = 0; q < kStageRing && e == hipSuccess; ++q)
+    e = hipEventCreateWithFlags(&st->slot[q].copied, hipEventDisableTiming);
   if (e != hipSuccess) {
     delete st;
     return hip_fail(e, "stream state");
@@ -110,18 +124,24 @@ fastnerf_status stream_state(hipStream_t s, StreamState **out) {
   return FASTNERF_OK;
 }
 
-fastnerf_status stream_views(StreamState *st, int n) {
-  if (n <= st->cap) return FASTNERF_OK;
-  HIP_TRY(hipEventSynchronize(st->staged));
-  if (st->views) HIP_TRY(hipFree(st->views));
-  if (st->views_host) HIP_TRY(hipHostFree(st->views_host));
-  st->views = nullptr;
-  st->views_host = nullptr;
-  st->cap = 0;
-  int cap = n < 64 ? 64 : n;
-  HIP_TRY(hipMalloc(&st->views, sizeof(DevView) * cap));
-  HIP_TRY(hipHostMalloc(&st->views_host, sizeof(DevView) * cap, hipHostMallocDefault));
-  st->cap = cap;
+// The staging slot of the next batch on this stream, holding at least n
+// descriptors; waits for the slot's previous copy (kStageRing batches back).
+fastnerf_status stream_slot(StreamState *st, int n, StageSlot **out) {
+  StageSlot *sl = &st->slot[st->next];
+  st->next = (st->next + 1) % kStageRing;
+  HIP_TRY(hipEventSynchronize(sl->copied));
+  if (n > sl->cap) {
+    if (sl->views) HIP_TRY(hipFree(sl->views));
+    if (sl->views_host) HIP_TRY(hipHostFree(sl->views_host));
+    sl->views = nullptr;
+    sl->views_host = nullptr;
+    sl->cap = 0;
+    int cap = n < 64 ? 64 : n;
+    HIP_TRY(hipMalloc(&sl->views, sizeof(DevView) * cap));
+    HIP_TRY(hipHostMalloc(&sl->views_host, sizeof(DevView) * cap, hipHostMallocDefault));
+    sl->cap = cap;
+  }
+  *out = sl;
   return FASTNERF_OK;
 }
 
@@ -131,15 +151,17 @@ struct LaunchPlan {
   int block, grid;
 };
 
-LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox) {
+LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox, int sched) {
   static std::mutex mu;
   static std::map<std::pair<int, int>, int> plans;  // (device, variant) -> resident blocks
   int dev = 0;
   (void)hipGetDevice(&dev);
   const bool lin = c->desc.pos_interp == FASTNERF_LINEAR;
   const bool sparse = c->desc.sparse && !vox;
-  const int variant = (int)c->desc.storage * 64 + (lin ? 32 : 0) + (vox ? 16 : 0) +
-                      (sparse ? 8 : 0) + (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
+  if (vox) sched = kSchedTiles;
+  const int variant = (int)c->desc.storage * 256 + sched * 64 + (lin ? 32 : 0) +
+                      (vox ? 16 : 0) + (sparse ? 8 : 0) +
+                      (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
   int blocks;
   {
     std::lock_guard<std::mutex> g(mu);
@@ -151,7 +173,8 @@ LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox) {
           cus < 1)
         cus = 1;
       const int per_cu = vox ? render_vox_occupancy((int)c->desc.storage, c->desc.D)
-                             : render_occupancy((int)c->desc.storage, lin, c->desc.D, sparse);
+                             : render_occupancy((int)c->desc.storage, lin, c->desc.D, sparse,
+                                                sched);
       it = plans.emplace(key, cus * (per_cu < 1 ? 1 : per_cu)).first;
     }
     blocks = it->second;
@@ -260,11 +283,37 @@ fastnerf_status check_render_params(int N, float eps) {
 
 float eps_limit(float eps) { return eps > 0.0f ? (float)log(1.0 / (double)eps) : INFINITY; }
 
+// Scheduling of fixed-N render launches (fastnerf_set_schedule).
+static std::atomic<int> g_schedule{FASTNERF_SCHEDULE_AUTO};
+
+// Launches of at most this many tiles (about two 800x800 views) cannot fill
+// the chip with the throughput kernels' waves, and are bound by the dependency
+// chains of their heaviest rays: AUTO gives them the wide kernel.
+constexpr int kWideMaxTiles = 20000;
+
+// The schedule of a launch (kSched*): AUTO takes the wide kernel for small
+// launches and tiles otherwise (measured on the paper-scale orbit, the refill
+// schedule was slower: its lanes hold rays of different tiles, so the lanes'
+// occupied samples per window are less alike and the gather rounds of a
+// window, the most over the wave's lanes, grow).
+int launch_schedule(const fastnerf_cache_s *c, bool vox, int total_tiles) {
+  (void)c;
+  if (vox) return kSchedTiles;
+  switch (g_schedule.load(std::memory_order_relaxed)) {
+    case FASTNERF_SCHEDULE_TILES: return kSchedTiles;
+    case FASTNERF_SCHEDULE_REFILL: return kSchedRefill;
+    case FASTNERF_SCHEDULE_WIDE: return kSchedWide;
+    default: break;
+  }
+  return total_tiles <= kWideMaxTiles ? kSchedWide : kSchedTiles;
+}
+
 fastnerf_status enqueue_render(fastnerf_cache_s *c, const RenderArgs &a0, int total_tiles,
-                               StreamState *st, hipStream_t s) {
+                               unsigned *counter, hipStream_t s) {
   RenderArgs a = a0;
-  const LaunchPlan p = launch_plan(c, total_tiles, a.vox != 0);
-  a.counter = st->counter;
+  a.sched = launch_schedule(c, a.vox != 0, total_tiles);
+  const LaunchPlan p = launch_plan(c, total_tiles, a.vox != 0, a.sched);
+  a.counter = counter;
   a.nwaves = (unsigned)p.grid * (p.block / kWave);
   a.total_tiles = total_tiles;
   hipError_t e = a.vox ? launch_render_vox((int)c->desc.storage, a, p.grid, s)
@@ -651,7 +700,7 @@ extern "C" fastnerf_status fastnerf_render(fastnerf_cache c, const float K[9],
   a.nviews = 1;
   a.vox = N == 0;
   const int tiles = ((W + 7) / 8) * ((H + 7) / 8);
-  return enqueue_render(c, a, tiles, ss, s);
+  return enqueue_render(c, a, tiles, ss->counter, s);
 }
 
 extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nviews,
@@ -676,28 +725,42 @@ extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nview
   }
   if (total > (int64_t)0x7FFFFFFF) return fail(FASTNERF_EINVAL, "too many tiles in one batch");
   StreamState *ss = nullptr;
+  StageSlot *sl = nullptr;
   st = stream_state(s, &ss);
-  if (st == FASTNERF_OK) st = stream_views(ss, nviews);
   if (st != FASTNERF_OK) return st;
-  HIP_TRY(hipEventSynchronize(ss->staged));  // the previous batch's descriptors were copied
+  std::lock_guard<std::mutex> guard(ss->mu);
+  st = stream_slot(ss, nviews, &sl);
+  if (st != FASTNERF_OK) return st;
   int tb = 0;
   for (int v = 0; v < nviews; ++v) {
     make_view(c, K + 9 * v, c2w + 12 * v, H[v], W[v], near_[v], far_[v], out[v], tb,
-              ss->views_host + v);
-    ss->views_host[v].N = N;
-    ss->views_host[v].lim = eps_limit(eps);
+              sl->views_host + v);
+    sl->views_host[v].N = N;
+    sl->views_host[v].lim = eps_limit(eps);
     tb += ((W[v] + 7) / 8) * ((H[v] + 7) / 8);
   }
-  HIP_TRY(hipMemcpyAsync(ss->views, ss->views_host, sizeof(DevView) * nviews,
+  HIP_TRY(hipMemcpyAsync(sl->views, sl->views_host, sizeof(DevView) * nviews,
                          hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(ss->staged, s));
+  HIP_TRY(hipEventRecord(sl->copied, s));
   RenderArgs a;
   memset(&a, 0, sizeof a);
   a.c = dev_cache(c);
-  a.views = ss->views;
+  a.views = sl->views;
   a.nviews = nviews;
   a.vox = N == 0;
-  return enqueue_render(c, a, (int)total, ss, s);
+  return enqueue_render(c, a, (int)total, ss->counter, s);
+}
+
+extern "C" fastnerf_status fastnerf_set_schedule(int32_t schedule) {
+  if (schedule != FASTNERF_SCHEDULE_AUTO && schedule != FASTNERF_SCHEDULE_TILES &&
+      schedule != FASTNERF_SCHEDULE_REFILL && schedule != FASTNERF_SCHEDULE_WIDE)
+    return fail(FASTNERF_EINVAL, "unknown schedule %d", schedule);
+  fnr::g_schedule.store(schedule, std::memory_order_relaxed);
+  return FASTNERF_OK;
+}
+
+extern "C" int32_t fastnerf_get_schedule(void) {
+  return fnr::g_schedule.load(std::memory_order_relaxed);
 }
 
 extern "C" fastnerf_status fastnerf_debug_lookup(fastnerf_cache c, int32_t n, const float *pts,

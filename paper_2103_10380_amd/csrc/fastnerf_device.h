@@ -25,10 +25,15 @@ constexpr int kMaxCh = 1 + 3 * kMaxD;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Nearest-voxel cell boundaries sit this many voxels below the faces: a point
-// on a face (or within rounding of it) takes the upper cell, also when the
-// sample spacing is commensurate with the grid and every sample lies on a face.
-constexpr float kTie = 1.0f / 512.0f;
+// The nearest voxel of grid coordinate g is floor(g + kTie): a point on a
+// voxel face takes the upper cell also when FP32 rounding puts it slightly
+// below the face. With a sample spacing commensurate with the grid (k = 768,
+// N = 192 across the box face to face) every sample lies on a face, and the
+// FP32 grid coordinates of such samples are within 1.3e-4 voxel of the exact
+// ones; kTie = 2^-11 (4.9e-4) clears that, and a point that it moves to the
+// upper cell lies within 6.2e-4 voxel of the face, where either cell is an
+// admissible nearest voxel under FP32 position error.
+constexpr float kTie = 1.0f / 2048.0f;
 
 // Largest stored brick distance (one byte per brick).
 constexpr int kDistCap = 63;
@@ -83,7 +88,13 @@ struct RenderArgs {
   const DevCache *caches;   // serving: per-scene caches (device), views[i].scene indexes it
   const int *dyn_total;     // serving: {tile count, view count} of the step (device)
   int vox;                  // 1: voxel traversal (every view has N = 0)
+  int sched;                // kSchedTiles, kSchedRefill or kSchedWide
 };
+
+// Schedules of a fixed-N render launch: one 8x8 tile per wave (tiles), the
+// wave-level ray queue (refill), tiles with more records in flight per lane
+// (wide, for launches with few tiles).
+constexpr int kSchedTiles = 0, kSchedRefill = 1, kSchedWide = 2;
 
 // ------------------------------------------------------------------ storage formats
 

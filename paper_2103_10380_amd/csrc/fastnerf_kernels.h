@@ -4,8 +4,9 @@
 
 namespace fnr {
 
-// Resident blocks per CU of the render kernel (0 if it cannot launch).
-int render_occupancy(int fmt, bool lin, int D, bool sparse);
+// Resident blocks per CU of the render kernel (0 if it cannot launch):
+// brick-sparse or dense cache, schedule kSched*.
+int render_occupancy(int fmt, bool lin, int D, bool sparse, int sched);
 // Tile queues of a render launch and the spacing of their counters (uints):
 // the counter buffer of a stream holds kQueueCounters uints.
 constexpr int kQueueCounters = 32 * 32;

@@ -43,29 +43,48 @@ template <int FMT, bool LIN> struct Batch {
       LIN ? 1 : (FMT == 0 ? FNR_BATCH_F32 : (FMT == 3 ? FNR_BATCH_F8 : FNR_BATCH_F16));
 };
 
-// Renders the rays of one 8x8 tile (one ray per lane) of view V with cache c.
-// SPARSE: a brick-sparse cache (bitgrid brick = storage brick = 8^3); the
-// stored brick of a flagged sample is its rank among the set bitgrid bits,
-// found from the bitgrid word already loaded by the window scan and the count
-// of set bits before that word (one more independent load), so the gather
-// needs no dependent table lookup.
-template <int FMT, int MAXD, bool LIN, bool SPARSE = false>
-__device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache &c,
-                                            const DevView &V, int lt, int lane) {
-  using RW = RecWords<FMT, MAXD>;
-  constexpr int B = Batch<FMT, LIN>::value;
-  const int W = V.W, H = V.H;
-  const int px = (lt % V.tiles_x) * 8 + (lane & 7);
-  const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
-  if (px >= W || py >= H) return;
-  const int N = V.N;
-  const int k = c.k;
-  const float kf = c.kf;
+// Records in flight per lane of the wide kernel, for launches too small to
+// fill the chip (a single view): more requests per ray at fewer waves per
+// SIMD shorten the dependency chain of the heaviest rays, which bounds such a
+// launch.
+#ifndef FNR_WIDE_F32
+#define FNR_WIDE_F32 4
+#endif
+#ifndef FNR_WIDE_F16
+#define FNR_WIDE_F16 4
+#endif
+#ifndef FNR_WIDE_F8
+#define FNR_WIDE_F8 8
+#endif
+template <int FMT, bool LIN> struct WideBatch {
+  static constexpr int value =
+      LIN ? 2 : (FMT == 0 ? FNR_WIDE_F32 : (FMT == 3 ? FNR_WIDE_F8 : FNR_WIDE_F16));
+};
 
-  // Ray set-up, once per ray, in FP64: the direction's small components and
-  // the box-entry distance are sensitive to rounding (near-grazing rays), and
-  // every sample position depends on them. Reading: pixel centres, OpenCV
-  // axes, unit direction.
+// Marching state of one ray (one lane): the interval start and direction in
+// grid coordinates, the sample spacing, the next window's first sample, the
+// composite so far and the per-ray colour weights.
+template <int FMT, int MAXD> struct Ray {
+  float og[3];   // grid coordinates of the interval start
+  float gd[3];   // grid coordinates per unit distance
+  float dt;      // sample spacing (distance)
+  float inv_step;  // 1 / (voxels advanced per sample in the max norm)
+  int i, N;      // first sample of the next window, samples per ray
+  float lim;     // ln(1/eps)
+  float tau, cr, cg, cb;
+  float cw[ColourWeights<FMT, MAXD>::n];
+  float4 *out;   // the pixel
+};
+
+// Ray set-up, once per ray, in FP64: the direction's small components and the
+// box-entry distance are sensitive to rounding (near-grazing rays), and every
+// sample position depends on them. Reading: pixel centres, OpenCV axes, unit
+// direction. Fills everything but the colour weights, and beta (the direction
+// lookup, once per ray) when the ray has samples to march; returns false for
+// a ray whose sample interval is empty.
+template <int FMT, int MAXD>
+__device__ __forceinline__ bool ray_setup(const DevCache &c, const DevView &V, int px, int py,
+                                          Ray<FMT, MAXD> &r, float *beta) {
   const double qx = (double)px + 0.5, qy = (double)py + 0.5;
   double ddx = fma(V.M[0], qx, fma(V.M[1], qy, V.M[2]));
   double ddy = fma(V.M[3], qx, fma(V.M[4], qy, V.M[5]));
@@ -74,7 +93,11 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
   ddx *= rn;
   ddy *= rn;
   ddz *= rn;
-
+  r.out = reinterpret_cast<float4 *>(V.out) + ((size_t)py * V.W + px);
+  r.tau = r.cr = r.cg = r.cb = 0.0f;
+  r.i = 0;
+  r.N = V.N;
+  r.lim = V.lim;
   // sample interval
   double t0 = V.near_, t1 = V.far_;
   if (c.in_box) {
@@ -91,219 +114,262 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
       }
     }
   }
-  float tau = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-  if (t1 > t0) {
-    float cw[ColourWeights<FMT, MAXD>::n];
-    float s0 = 1.0f;
-    {
-      float beta[MAXD];
-      dir_lookup<MAXD>(c, (float)ddx, (float)ddy, (float)ddz, beta);
+  if (!(t1 > t0)) return false;
+  dir_lookup<MAXD>(c, (float)ddx, (float)ddy, (float)ddz, beta);
+  r.dt = (float)((t1 - t0) / (double)V.N);
+  // grid coordinates of the interval start and the per-distance step;
+  // sample i sits at distance (i + 1/2) dt past the start
+  r.og[0] = (float)((fma(t0, ddx, V.o[0]) - c.bmin[0]) * c.inv_h[0]);
+  r.og[1] = (float)((fma(t0, ddy, V.o[1]) - c.bmin[1]) * c.inv_h[1]);
+  r.og[2] = (float)((fma(t0, ddz, V.o[2]) - c.bmin[2]) * c.inv_h[2]);
+  r.gd[0] = (float)(ddx * c.inv_h[0]);
+  r.gd[1] = (float)(ddy * c.inv_h[1]);
+  r.gd[2] = (float)(ddz * c.inv_h[2]);
+  const float vstep = r.dt * fmaxf(fabsf(r.gd[0]), fmaxf(fabsf(r.gd[1]), fabsf(r.gd[2])));
+  r.inv_step = 1.0f / vstep;
+  return true;
+}
+
+// Per-ray colour weights from beta: beta itself, or for E4M3 records beta
+// times the channel scales (Eq. 5 with the dequantisation folded in).
+template <int FMT, int MAXD>
+__device__ __forceinline__ void ray_weights(const DevCache &c, const float *beta,
+                                            Ray<FMT, MAXD> &r) {
 #pragma unroll
-      for (int d = 0; d < MAXD; ++d) {
-        if (FMT == 3) {
+  for (int d = 0; d < MAXD; ++d) {
+    if (FMT == 3) {
 #pragma unroll
-          for (int ch = 0; ch < 3; ++ch) cw[3 * d + ch] = beta[d] * c.scales[1 + 3 * d + ch];
-        } else {
-          cw[d] = beta[d];
-        }
-      }
-      if (FMT == 3) s0 = c.scales[0];
-    }
-    const float dt = (float)((t1 - t0) / (double)N);
-    // grid coordinates of the interval start and the per-distance step;
-    // sample i sits at distance (i + 1/2) dt past the start
-    const float ogx = (float)((fma(t0, ddx, V.o[0]) - c.bmin[0]) * c.inv_h[0]);
-    const float ogy = (float)((fma(t0, ddy, V.o[1]) - c.bmin[1]) * c.inv_h[1]);
-    const float ogz = (float)((fma(t0, ddz, V.o[2]) - c.bmin[2]) * c.inv_h[2]);
-    const float gdx = (float)(ddx * c.inv_h[0]), gdy = (float)(ddy * c.inv_h[1]),
-                gdz = (float)(ddz * c.inv_h[2]);
-    // Samples are taken in windows of kWin: the occupancy bits of a window
-    // are fetched with independent loads and one wait, then its occupied
-    // samples are gathered and composited in order, B records in flight at a
-    // time. With the same wait, the brick distance d of the window's last
-    // sample is read: d >= 2 (bricks, max norm, to the nearest occupied brick)
-    // proves that every point within (d - 1) brick edges of that sample lies
-    // in an empty brick, so the next window starts past the last sample so
-    // proven empty. Samples advance vstep voxels each in the max norm; half a
-    // voxel of margin covers FP32 position rounding.
-    const float vstep = dt * fmaxf(fabsf(gdx), fmaxf(fabsf(gdy), fabsf(gdz)));
-    const float inv_step = 1.0f / vstep;
-    const float bedge = (float)(1 << c.oshift);
-    int i = 0;
-    bool alive = true;
-    // record registers: loaded only by lanes with a sample in the slot; the
-    // others keep earlier (defined) values, which the composite selects away
-    uint32_t w[B][RecWords<FMT, MAXD>::nwords];
-#pragma unroll
-    for (int b = 0; b < B; ++b)
-#pragma unroll
-      for (int q = 0; q < RecWords<FMT, MAXD>::nwords; ++q) w[b][q] = 0u;
-    while (alive) {
-      uint32_t mask = 0u;
-      int next = i + kWin;
-      uint32_t sslot[SPARSE ? kWin : 1];  // stored brick of each sample (SPARSE)
-      {
-        // a cache without a bitgrid has one all-ones word and one zero
-        // distance, with oshift past every coordinate bit
-        uint32_t word[kWin], bitpos[kWin], rk[SPARSE ? kWin : 1], dlast = 0u;
-        bool in[kWin];
-#pragma unroll
-        for (int j = 0; j < kWin; ++j) {
-          const float t = ((float)(i + j) + 0.5f) * dt;
-          const float gx = fmaf(t, gdx, ogx), gy = fmaf(t, gdy, ogy), gz = fmaf(t, gdz, ogz);
-          // inside the box: 0 <= g <= k on every axis
-          in[j] = (i + j < N) && fminf(fminf(gx, gy), gz) >= 0.0f &&
-                  fmaxf(fmaxf(gx, gy), gz) <= kf;
-          // clamped voxel: always a valid address, even when not inside
-          const int x = min(max((int)(gx + kTie), 0), k - 1),
-                    y = min(max((int)(gy + kTie), 0), k - 1),
-                    z = min(max((int)(gz + kTie), 0), k - 1);
-          const uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo +
-                                (uint32_t)(y >> c.oshift)) * (uint32_t)c.nbo +
-                               (uint32_t)(x >> c.oshift);
-          word[j] = __ldg(c.occ + (bit >> 5));
-          bitpos[j] = bit & 31u;
-          if (SPARSE) rk[(SPARSE ? j : 0)] = __ldg(c.rank + (bit >> 5));
-          if (j == kWin - 1) dlast = __ldg(c.dist + bit);
-        }
-#pragma unroll
-        for (int j = 0; j < kWin; ++j)
-          mask |= (uint32_t)(in[j] && ((word[j] >> bitpos[j]) & 1u)) << j;
-        if (SPARSE) {
-#pragma unroll
-          for (int j = 0; j < kWin; ++j)
-            sslot[(SPARSE ? j : 0)] = 1u + rk[(SPARSE ? j : 0)] +
-                                      (uint32_t)__builtin_popcount(word[j] & ((1u << bitpos[j]) - 1u));
-        }
-        if (dlast >= 2u) {
-          const float run = fminf(((float)(dlast - 1u) * bedge - 0.5f) * inv_step, (float)N);
-          next += (int)run;
-        }
-      }
-      while (mask != 0u && alive) {
-        // the next B occupied samples; slots past the last one repeat the
-        // first sample's voxel, so every load has a valid (cached) address
-        int vx[B], vy[B], vz[B];
-        float wx[B], wy[B], wz[B];
-        uint32_t sb[B];
-        bool have[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-          have[b] = mask != 0u;
-          sb[b] = 0u;
-          if (have[b]) {
-            const int j = __builtin_ctz(mask);
-            mask &= mask - 1u;
-            if (SPARSE) {  // j varies across lanes: a select chain
-              uint32_t v = sslot[0];
-#pragma unroll
-              for (int q = 1; q < kWin; ++q) v = q == j ? sslot[(SPARSE ? q : 0)] : v;
-              sb[b] = v;
-            }
-            const float t = ((float)(i + j) + 0.5f) * dt;
-            const float gx = fmaf(t, gdx, ogx), gy = fmaf(t, gdy, ogy), gz = fmaf(t, gdz, ogz);
-            if (LIN) {
-              const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
-              const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
-              vx[b] = (int)fx0;
-              vy[b] = (int)fy0;
-              vz[b] = (int)fz0;
-              wx[b] = hx - fx0;
-              wy[b] = hy - fy0;
-              wz[b] = hz - fz0;
-            } else {
-              vx[b] = min((int)(gx + kTie), k - 1);
-              vy[b] = min((int)(gy + kTie), k - 1);
-              vz[b] = min((int)(gz + kTie), k - 1);
-              wx[b] = wy[b] = wz[b] = 0.0f;
-            }
-          } else {
-            vx[b] = vx[0];
-            vy[b] = vy[0];
-            vz[b] = vz[0];
-            wx[b] = wy[b] = wz[b] = 0.0f;
-            sb[b] = sb[0];
-          }
-        }
-        if (!LIN) {
-          uint64_t off[B];
-#pragma unroll
-          for (int b = 0; b < B; ++b)
-            off[b] = SPARSE ? record_offset_in(c, sb[b], vx[b], vy[b], vz[b])
-                            : record_offset(c, vx[b], vy[b], vz[b]);
-#pragma unroll
-          for (int b = 0; b < B; ++b)
-            if (have[b] && alive) load_record<FMT, MAXD>(c, off[b], w[b]);
-          // all B records are requested before the first is used, each only
-          // by the lanes that have a sample in its slot (the others issue no
-          // memory request); an unused slot (past the window's last occupied
-          // sample, or after the stop) adds zero optical depth and zero colour
-#pragma unroll
-          for (int b = 0; b < B; ++b) {
-            // no contraction of sigma*dt into the optical-depth sum: every
-            // slot, and every occupancy setting, rounds alike
-#pragma clang fp contract(off)
-            const bool use = have[b] && alive;
-            const float s = rec_sigma<FMT>(w[b], s0);
-            float r, g, bl;
-            rec_colour<FMT, MAXD>(w[b], cw, r, g, bl);
-            r = use ? r : 0.0f;
-            g = use ? g : 0.0f;
-            bl = use ? bl : 0.0f;
-            const float sd = use ? s * dt : 0.0f;
-            const float wgt = expf(-tau) * -expm1f(-sd);
-            cr = fmaf(wgt, r, cr);
-            cg = fmaf(wgt, g, cg);
-            cb = fmaf(wgt, bl, cb);
-            tau = tau + sd;
-            alive = alive && !(tau > V.lim);  // every later sample would be stopped
-          }
-        } else {
-#pragma unroll
-          for (int b = 0; b < B; ++b) {
-            if (!have[b] || !alive) continue;
-            uint32_t w[8][RW::nwords];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int x = min(max(vx[b] + (q & 1), 0), k - 1);
-              const int y = min(max(vy[b] + ((q >> 1) & 1), 0), k - 1);
-              const int z = min(max(vz[b] + ((q >> 2) & 1), 0), k - 1);
-              load_record<FMT, MAXD>(c, record_offset(c, x, y, z), w[q]);
-            }
-            float s = 0.f, r = 0.f, g = 0.f, bl = 0.f;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const float wq = ((q & 1) ? wx[b] : 1.0f - wx[b]) *
-                               (((q >> 1) & 1) ? wy[b] : 1.0f - wy[b]) *
-                               (((q >> 2) & 1) ? wz[b] : 1.0f - wz[b]);
-              float rq, gq, bq;
-              rec_colour<FMT, MAXD>(w[q], cw, rq, gq, bq);
-              s = fmaf(wq, rec_sigma<FMT>(w[q], s0), s);
-              r = fmaf(wq, rq, r);
-              g = fmaf(wq, gq, g);
-              bl = fmaf(wq, bq, bl);
-            }
-            const float sd = s * dt;
-            const float wgt = expf(-tau) * -expm1f(-sd);
-            cr = fmaf(wgt, r, cr);
-            cg = fmaf(wgt, g, cg);
-            cb = fmaf(wgt, bl, cb);
-            tau = tau + sd;
-            if (tau > V.lim) alive = false;
-          }
-        }
-      }
-      i = next;
-      if (i >= N) alive = false;
+      for (int ch = 0; ch < 3; ++ch) r.cw[3 * d + ch] = beta[d] * c.scales[1 + 3 * d + ch];
+    } else {
+      r.cw[d] = beta[d];
     }
   }
-  const float T = expf(-tau);
+}
+
+// The pixel: RGB = C + T bg, A = 1 - T (T = exp(-tau)).
+template <int FMT, int MAXD>
+__device__ __forceinline__ void ray_finish(const DevCache &c, const Ray<FMT, MAXD> &r) {
+  const float T = expf(-r.tau);
   float4 res;
-  res.x = fmaf(T, c.bg[0], cr);
-  res.y = fmaf(T, c.bg[1], cg);
-  res.z = fmaf(T, c.bg[2], cb);
-  res.w = -expm1f(-tau);
-  reinterpret_cast<float4 *>(V.out)[(size_t)py * W + px] = res;
+  res.x = fmaf(T, c.bg[0], r.cr);
+  res.y = fmaf(T, c.bg[1], r.cg);
+  res.z = fmaf(T, c.bg[2], r.cb);
+  res.w = -expm1f(-r.tau);
+  *r.out = res;
+}
+
+// One window of kWin samples of a live ray: the occupancy bits of the window
+// are fetched with independent loads and one wait, then its occupied samples
+// are gathered and composited in order, B records in flight at a time. With
+// the same wait, the brick distance d of the window's last sample is read:
+// d >= 2 (bricks, max norm, to the nearest occupied brick) proves that every
+// point within (d - 1) brick edges of that sample lies in an empty brick, so
+// the next window starts past the last sample so proven empty. Samples advance
+// vstep voxels each in the max norm; half a voxel of margin covers FP32
+// position rounding. alive turns false when the ray stops (optical depth past
+// ln(1/eps)) or runs out of samples. Lanes enter with alive false and do
+// nothing (the wave runs the window for its live lanes).
+// SPARSE: a brick-sparse cache (bitgrid brick = storage brick = 8^3); the
+// stored brick of a flagged sample is its rank among the set bitgrid bits,
+// found from the bitgrid word already loaded by the window scan and the count
+// of set bits before that word (one more independent load), so the gather
+// needs no dependent table lookup.
+template <int FMT, int MAXD, bool LIN, bool SPARSE, int B = Batch<FMT, LIN>::value>
+__device__ __forceinline__ void ray_window(const DevCache &c, Ray<FMT, MAXD> &r, bool &alive,
+                                           float s0) {
+  using RW = RecWords<FMT, MAXD>;
+  const int k = c.k;
+  const float kf = c.kf;
+  const int N = r.N;
+  const float dt = r.dt;
+  const float bedge = (float)(1 << c.oshift);
+  uint32_t mask = 0u;
+  int next = r.i + kWin;
+  uint32_t sslot[SPARSE ? kWin : 1];  // stored brick of each sample (SPARSE)
+  if (alive) {
+    // a cache without a bitgrid has one all-ones word and one zero
+    // distance, with oshift past every coordinate bit
+    uint32_t word[kWin], bitpos[kWin], rk[SPARSE ? kWin : 1], dlast = 0u;
+    bool in[kWin];
+#pragma unroll
+    for (int j = 0; j < kWin; ++j) {
+      const float t = ((float)(r.i + j) + 0.5f) * dt;
+      const float gx = fmaf(t, r.gd[0], r.og[0]), gy = fmaf(t, r.gd[1], r.og[1]),
+                  gz = fmaf(t, r.gd[2], r.og[2]);
+      // inside the box: 0 <= g <= k on every axis
+      in[j] = (r.i + j < N) && fminf(fminf(gx, gy), gz) >= 0.0f &&
+              fmaxf(fmaxf(gx, gy), gz) <= kf;
+      // clamped voxel: always a valid address, even when not inside
+      const int x = min(max((int)(gx + kTie), 0), k - 1),
+                y = min(max((int)(gy + kTie), 0), k - 1),
+                z = min(max((int)(gz + kTie), 0), k - 1);
+      const uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo +
+                            (uint32_t)(y >> c.oshift)) * (uint32_t)c.nbo +
+                           (uint32_t)(x >> c.oshift);
+      word[j] = __ldg(c.occ + (bit >> 5));
+      bitpos[j] = bit & 31u;
+      if (SPARSE) rk[(SPARSE ? j : 0)] = __ldg(c.rank + (bit >> 5));
+      if (j == kWin - 1) dlast = __ldg(c.dist + bit);
+    }
+#pragma unroll
+    for (int j = 0; j < kWin; ++j)
+      mask |= (uint32_t)(in[j] && ((word[j] >> bitpos[j]) & 1u)) << j;
+    if (SPARSE) {
+#pragma unroll
+      for (int j = 0; j < kWin; ++j)
+        sslot[(SPARSE ? j : 0)] = 1u + rk[(SPARSE ? j : 0)] +
+                                  (uint32_t)__builtin_popcount(word[j] & ((1u << bitpos[j]) - 1u));
+    }
+    if (dlast >= 2u) {
+      const float run = fminf(((float)(dlast - 1u) * bedge - 0.5f) * r.inv_step, (float)N);
+      next += (int)run;
+    }
+  }
+  // record registers: loaded only by lanes with a sample in the slot; the
+  // others keep earlier (defined) values, which the composite selects away
+  uint32_t w[B][RW::nwords];
+#pragma unroll
+  for (int b = 0; b < B; ++b)
+#pragma unroll
+    for (int q = 0; q < RW::nwords; ++q) w[b][q] = 0u;
+  while (mask != 0u && alive) {
+    // the next B occupied samples; slots past the last one repeat the
+    // first sample's voxel, so every load has a valid (cached) address
+    int vx[B], vy[B], vz[B];
+    float wx[B], wy[B], wz[B];
+    uint32_t sb[B];
+    bool have[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      have[b] = mask != 0u;
+      sb[b] = 0u;
+      if (have[b]) {
+        const int j = __builtin_ctz(mask);
+        mask &= mask - 1u;
+        if (SPARSE) {  // j varies across lanes: a select chain
+          uint32_t v = sslot[0];
+#pragma unroll
+          for (int q = 1; q < kWin; ++q) v = q == j ? sslot[(SPARSE ? q : 0)] : v;
+          sb[b] = v;
+        }
+        const float t = ((float)(r.i + j) + 0.5f) * dt;
+        const float gx = fmaf(t, r.gd[0], r.og[0]), gy = fmaf(t, r.gd[1], r.og[1]),
+                    gz = fmaf(t, r.gd[2], r.og[2]);
+        if (LIN) {
+          const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
+          const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
+          vx[b] = (int)fx0;
+          vy[b] = (int)fy0;
+          vz[b] = (int)fz0;
+          wx[b] = hx - fx0;
+          wy[b] = hy - fy0;
+          wz[b] = hz - fz0;
+        } else {
+          vx[b] = min((int)(gx + kTie), k - 1);
+          vy[b] = min((int)(gy + kTie), k - 1);
+          vz[b] = min((int)(gz + kTie), k - 1);
+          wx[b] = wy[b] = wz[b] = 0.0f;
+        }
+      } else {
+        vx[b] = vx[0];
+        vy[b] = vy[0];
+        vz[b] = vz[0];
+        wx[b] = wy[b] = wz[b] = 0.0f;
+        sb[b] = sb[0];
+      }
+    }
+    if (!LIN) {
+      uint64_t off[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        off[b] = SPARSE ? record_offset_in(c, sb[b], vx[b], vy[b], vz[b])
+                        : record_offset(c, vx[b], vy[b], vz[b]);
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (have[b] && alive) load_record<FMT, MAXD>(c, off[b], w[b]);
+      // all B records are requested before the first is used, each only
+      // by the lanes that have a sample in its slot (the others issue no
+      // memory request); an unused slot (past the window's last occupied
+      // sample, or after the stop) adds zero optical depth and zero colour
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        // no contraction of sigma*dt into the optical-depth sum: every
+        // slot, and every occupancy setting, rounds alike
+#pragma clang fp contract(off)
+        const bool use = have[b] && alive;
+        const float s = rec_sigma<FMT>(w[b], s0);
+        float cr, cg, cb;
+        rec_colour<FMT, MAXD>(w[b], r.cw, cr, cg, cb);
+        cr = use ? cr : 0.0f;
+        cg = use ? cg : 0.0f;
+        cb = use ? cb : 0.0f;
+        const float sd = use ? s * dt : 0.0f;
+        const float wgt = expf(-r.tau) * -expm1f(-sd);
+        r.cr = fmaf(wgt, cr, r.cr);
+        r.cg = fmaf(wgt, cg, r.cg);
+        r.cb = fmaf(wgt, cb, r.cb);
+        r.tau = r.tau + sd;
+        alive = alive && !(r.tau > r.lim);  // every later sample would be stopped
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (!have[b] || !alive) continue;
+        uint32_t wq[8][RW::nwords];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int x = min(max(vx[b] + (q & 1), 0), k - 1);
+          const int y = min(max(vy[b] + ((q >> 1) & 1), 0), k - 1);
+          const int z = min(max(vz[b] + ((q >> 2) & 1), 0), k - 1);
+          load_record<FMT, MAXD>(c, record_offset(c, x, y, z), wq[q]);
+        }
+        float s = 0.f, cr = 0.f, cg = 0.f, cb = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float wt = ((q & 1) ? wx[b] : 1.0f - wx[b]) *
+                           (((q >> 1) & 1) ? wy[b] : 1.0f - wy[b]) *
+                           (((q >> 2) & 1) ? wz[b] : 1.0f - wz[b]);
+          float rq, gq, bq;
+          rec_colour<FMT, MAXD>(wq[q], r.cw, rq, gq, bq);
+          s = fmaf(wt, rec_sigma<FMT>(wq[q], s0), s);
+          cr = fmaf(wt, rq, cr);
+          cg = fmaf(wt, gq, cg);
+          cb = fmaf(wt, bq, cb);
+        }
+        const float sd = s * dt;
+        const float wgt = expf(-r.tau) * -expm1f(-sd);
+        r.cr = fmaf(wgt, cr, r.cr);
+        r.cg = fmaf(wgt, cg, r.cg);
+        r.cb = fmaf(wgt, cb, r.cb);
+        r.tau = r.tau + sd;
+        if (r.tau > r.lim) alive = false;
+      }
+    }
+  }
+  if (alive) {
+    r.i = next;
+    if (r.i >= N) alive = false;
+  }
+}
+
+// Renders the rays of one 8x8 tile (one ray per lane) of view V with cache c:
+// set-up, windows until the ray stops, the pixel.
+template <int FMT, int MAXD, bool LIN, bool SPARSE = false, int B = Batch<FMT, LIN>::value>
+__device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache &c,
+                                            const DevView &V, int lt, int lane) {
+  (void)a;
+  const int px = (lt % V.tiles_x) * 8 + (lane & 7);
+  const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
+  if (px >= V.W || py >= V.H) return;
+  Ray<FMT, MAXD> r;
+  float beta[MAXD];
+  bool alive = ray_setup<FMT, MAXD>(c, V, px, py, r, beta);
+  if (alive) {
+    ray_weights<FMT, MAXD>(c, beta, r);
+    const float s0 = FMT == 3 ? c.scales[0] : 1.0f;
+    while (alive) ray_window<FMT, MAXD, LIN, SPARSE, B>(c, r, alive, s0);
+  }
+  ray_finish<FMT, MAXD>(c, r);
 }
 
 // ------------------------------------------------------------------ voxel traversal
@@ -315,15 +381,15 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
 constexpr int kVWin = FNR_VWIN;
 constexpr float kVInf = 3.0e38f;
 
-// Distance (from the interval start, in t) to the next crossing of a cell
-// boundary along one axis from cell c, moving by step (+1/-1); cell
-// boundaries sit at grid coordinates i - kTie for i = 1..k-1 (the first and
-// last cells end at the box faces, where the interval ends).
+// Distance (from the interval start, in t) to the next crossing of a voxel
+// face along one axis from cell c, moving by step (+1/-1); interior faces sit
+// at grid coordinates i = 1..k-1 (the first and last cells end at the box
+// faces, where the interval ends).
 __device__ __forceinline__ float vox_next(int c, int step, int k, float og, float igd) {
   if (step == 0) return kVInf;
-  const int b = step > 0 ? c + 1 : c;  // boundary index
+  const int b = step > 0 ? c + 1 : c;  // face index
   if (b < 1 || b > k - 1) return kVInf;
-  return ((float)b - kTie - og) * igd;
+  return ((float)b - og) * igd;
 }
 
 // Renders the rays of one 8x8 tile by visiting every voxel each ray crosses
@@ -412,9 +478,9 @@ __device__ __forceinline__ void render_tile_vox(const RenderArgs &a, const DevCa
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
           const float g = fmaf(sc, gd[ax], og[ax]);
-          cell[ax] = min(max((int)floorf(g + kTie), 0), k - 1);
+          cell[ax] = min(max((int)floorf(g), 0), k - 1);
           sn[ax] = vox_next(cell[ax], step[ax], k, og[ax], igd[ax]);
-          if (sn[ax] <= sc) {  // on (or rounded past) the boundary: the next cell
+          if (sn[ax] <= sc) {  // on (or rounded past) the face: the next cell
             cell[ax] = min(max(cell[ax] + step[ax], 0), k - 1);
             sn[ax] = vox_next(cell[ax], step[ax], k, og[ax], igd[ax]);
           }
@@ -588,7 +654,7 @@ __device__ __forceinline__ int view_of_tile(const RenderArgs &a, int tile, int n
 // One cache, one storage format: single views (inline descriptor) or a batch
 // of views in one launch. Each wave renders one 8x8 tile at a time, one ray
 // per lane, taking tiles from its queue until the queue is empty.
-template <int FMT, int MAXD, bool LIN, bool SPARSE>
+template <int FMT, int MAXD, bool LIN, bool SPARSE, int B = Batch<FMT, LIN>::value>
 __device__ __forceinline__ void render_queue(const RenderArgs &a) {
   const int lane = threadIdx.x & (kWave - 1);
   const Queue Q = make_queue(a, a.total_tiles);
@@ -597,10 +663,141 @@ __device__ __forceinline__ void render_queue(const RenderArgs &a) {
     if (tile < 0) break;
     if (a.views) {
       const DevView V = a.views[view_of_tile(a, tile, a.nviews)];
-      render_tile<FMT, MAXD, LIN, SPARSE>(a, a.c, V, tile - V.tile_begin + V.tile_offset, lane);
+      render_tile<FMT, MAXD, LIN, SPARSE, B>(a, a.c, V, tile - V.tile_begin + V.tile_offset,
+                                             lane);
     } else {
-      render_tile<FMT, MAXD, LIN, SPARSE>(a, a.c, a.v0, tile, lane);
+      render_tile<FMT, MAXD, LIN, SPARSE, B>(a, a.c, a.v0, tile, lane);
     }
+  }
+  queue_retire(Q, lane);
+}
+
+// Ray refill (the wave-level ray queue): a wave keeps its lanes busy across
+// tiles instead of holding a tile until its slowest ray stops. After every
+// window the wave takes a ballot of its live lanes; once at least kRefillMin
+// lanes have retired their rays, it hands them rays from a per-wave pool in
+// LDS, and when the pool is empty it takes the next tile from its queue, sets
+// up that tile's 64 rays (one per lane, in parallel), writes the pixels of
+// rays that miss the box, and compacts the others into the pool (ballot and
+// prefix count). A ray is computed by one lane from set-up to pixel with the
+// same arithmetic as in render_tile, so the image is bitwise the same; only
+// the lane and the time at which a ray runs change.
+#ifndef FNR_REFILL_MIN
+#define FNR_REFILL_MIN 16
+#endif
+constexpr int kRefillMin = FNR_REFILL_MIN;
+
+// Pool fields of a set-up ray (32-bit words): og[3], gd[3], dt, inv_step, N,
+// lim, the pixel address (two words), beta[MAXD].
+template <int MAXD> struct PoolFields {
+  static constexpr int n = 12 + MAXD;
+};
+
+template <int FMT, int MAXD>
+__device__ __forceinline__ void pool_put(uint32_t (*P)[kWave], int e, const Ray<FMT, MAXD> &r,
+                                         const float *beta) {
+  P[0][e] = __float_as_uint(r.og[0]);
+  P[1][e] = __float_as_uint(r.og[1]);
+  P[2][e] = __float_as_uint(r.og[2]);
+  P[3][e] = __float_as_uint(r.gd[0]);
+  P[4][e] = __float_as_uint(r.gd[1]);
+  P[5][e] = __float_as_uint(r.gd[2]);
+  P[6][e] = __float_as_uint(r.dt);
+  P[7][e] = __float_as_uint(r.inv_step);
+  P[8][e] = (uint32_t)r.N;
+  P[9][e] = __float_as_uint(r.lim);
+  const uint64_t op = reinterpret_cast<uint64_t>(r.out);
+  P[10][e] = (uint32_t)op;
+  P[11][e] = (uint32_t)(op >> 32);
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) P[12 + d][e] = __float_as_uint(beta[d]);
+}
+
+template <int FMT, int MAXD>
+__device__ __forceinline__ void pool_get(const DevCache &c, uint32_t (*P)[kWave], int e,
+                                         Ray<FMT, MAXD> &r) {
+  r.og[0] = __uint_as_float(P[0][e]);
+  r.og[1] = __uint_as_float(P[1][e]);
+  r.og[2] = __uint_as_float(P[2][e]);
+  r.gd[0] = __uint_as_float(P[3][e]);
+  r.gd[1] = __uint_as_float(P[4][e]);
+  r.gd[2] = __uint_as_float(P[5][e]);
+  r.dt = __uint_as_float(P[6][e]);
+  r.inv_step = __uint_as_float(P[7][e]);
+  r.N = (int)P[8][e];
+  r.lim = __uint_as_float(P[9][e]);
+  r.out = reinterpret_cast<float4 *>((uint64_t)P[10][e] | ((uint64_t)P[11][e] << 32));
+  float beta[MAXD];
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) beta[d] = __uint_as_float(P[12 + d][e]);
+  ray_weights<FMT, MAXD>(c, beta, r);
+  r.i = 0;
+  r.tau = r.cr = r.cg = r.cb = 0.0f;
+}
+
+template <int FMT, int MAXD, bool LIN, bool SPARSE>
+__device__ __forceinline__ void render_refill(const RenderArgs &a) {
+  __shared__ uint32_t pool[kBlock / kWave][PoolFields<MAXD>::n][kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t(*P)[kWave] = pool[threadIdx.x / kWave];
+  const DevCache &c = a.c;
+  const Queue Q = make_queue(a, a.total_tiles);
+  const float s0 = FMT == 3 ? c.scales[0] : 1.0f;
+  const uint64_t below = (1ull << lane) - 1ull;  // the lanes before this one
+  Ray<FMT, MAXD> r;
+  bool alive = false;
+  int pend = 0;        // set-up rays waiting in the pool (wave-uniform)
+  bool qdone = false;  // the wave's tile queue is empty (wave-uniform)
+  for (;;) {
+    uint64_t freem = __ballot(!alive);
+    if (__popcll(freem) >= kRefillMin) {
+      for (;;) {
+        const int nfree = __popcll(freem);
+        if (nfree == 0) break;
+        if (pend == 0) {
+          if (qdone) break;
+          const int tile = queue_fetch(Q, lane);
+          if (tile < 0) {
+            qdone = true;
+            break;
+          }
+          const DevView V = a.views ? a.views[view_of_tile(a, tile, a.nviews)] : a.v0;
+          const int lt = a.views ? tile - V.tile_begin + V.tile_offset : tile;
+          const int px = (lt % V.tiles_x) * 8 + (lane & 7);
+          const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
+          bool march = false;
+          Ray<FMT, MAXD> nr;
+          float beta[MAXD];
+          if (px < V.W && py < V.H) {
+            march = ray_setup<FMT, MAXD>(c, V, px, py, nr, beta);
+            if (!march) ray_finish<FMT, MAXD>(c, nr);  // the background
+          }
+          const uint64_t m = __ballot(march);
+          if (march) pool_put<FMT, MAXD>(P, __popcll(m & below), nr, beta);
+          pend = __popcll(m);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          continue;
+        }
+        // free lanes take the pool's last entries
+        const int take = min(nfree, pend);
+        const int rank = __popcll(freem & below);
+        if (!alive && rank < take) {
+          pool_get<FMT, MAXD>(c, P, pend - 1 - rank, r);
+          alive = true;
+        }
+        pend -= take;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        freem = __ballot(!alive);
+      }
+    }
+    if (__ballot(alive) == 0ull) break;  // queue empty, pool empty, every ray done
+    const bool was = alive;
+    ray_window<FMT, MAXD, LIN, SPARSE>(c, r, alive, s0);
+    if (was && !alive) ray_finish<FMT, MAXD>(c, r);
   }
   queue_retire(Q, lane);
 }
@@ -620,6 +817,26 @@ __global__ void __launch_bounds__(kBlock)
   render_queue<FMT, MAXD, LIN, false>(a);
 }
 
+// The same with more records in flight per lane (WideBatch), for launches
+// with few tiles.
+template <int FMT, int MAXD, bool LIN>
+__global__ void __launch_bounds__(kBlock) k_render_wide(RenderArgs a) {
+  render_queue<FMT, MAXD, LIN, false, WideBatch<FMT, LIN>::value>(a);
+}
+
+// The same over the refill schedule (wave-level ray queue), compiled for 4
+// waves per SIMD with nearest lookups in FP32/FP16/BF16 and up to 8 components
+// (as the tile kernel runs).
+constexpr int refill_waves(int fmt, int maxd, bool lin) {
+  return fmt != 3 && maxd <= 8 && !lin ? 4 : 1;
+}
+template <int FMT, int MAXD, bool LIN>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(refill_waves(FMT, MAXD, LIN))))
+    k_render_refill(RenderArgs a) {
+  render_refill<FMT, MAXD, LIN, false>(a);
+}
+
 // The brick-sparse render kernel. Its slot arithmetic holds one more register
 // per window sample; W waves per SIMD are asked of the compiler so that it
 // keeps the dense kernel's occupancy (a few spilled bytes at most), which
@@ -629,6 +846,15 @@ template <int FMT, int MAXD, int W>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W, W)))
 k_render_sparse(RenderArgs a) {
   render_queue<FMT, MAXD, false, true>(a);
+}
+template <int FMT, int MAXD, int W>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W, W)))
+k_render_sparse_refill(RenderArgs a) {
+  render_refill<FMT, MAXD, false, true>(a);
+}
+template <int FMT, int MAXD>
+__global__ void __launch_bounds__(kBlock) k_render_sparse_wide(RenderArgs a) {
+  render_queue<FMT, MAXD, false, true, WideBatch<FMT, false>::value>(a);
 }
 constexpr int sparse_waves(int fmt, int maxd) { return maxd == 16 ? 2 : (fmt == 3 ? 3 : 4); }
 
@@ -924,57 +1150,62 @@ __global__ void k_lookup(DevCache c, int n, const float *__restrict__ pts,
 
 namespace {
 
+// The render kernel of a launch: schedule (kSchedTiles, kSchedRefill,
+// kSchedWide) and cache kind (dense or brick-sparse).
 template <int FMT, int MAXD, bool LIN>
-hipError_t launch_render_t(const RenderArgs &a, int grid, hipStream_t s) {
+const void *render_kernel(int sched, bool sparse) {
   if constexpr (!LIN) {
-    if (a.c.slot) {
-      hipLaunchKernelGGL((k_render_sparse<FMT, MAXD, sparse_waves(FMT, MAXD)>), dim3(grid), dim3(kBlock), 0, s, a);
-      return hipGetLastError();
+    if (sparse) {
+      if (sched == kSchedRefill)
+        return (const void *)k_render_sparse_refill<FMT, MAXD, sparse_waves(FMT, MAXD)>;
+      if (sched == kSchedWide) return (const void *)k_render_sparse_wide<FMT, MAXD>;
+      return (const void *)k_render_sparse<FMT, MAXD, sparse_waves(FMT, MAXD)>;
     }
   }
-  hipLaunchKernelGGL((k_render<FMT, MAXD, LIN>), dim3(grid), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+  if (sched == kSchedRefill) return (const void *)k_render_refill<FMT, MAXD, LIN>;
+  if (sched == kSchedWide) return (const void *)k_render_wide<FMT, MAXD, LIN>;
+  return (const void *)k_render<FMT, MAXD, LIN>;
 }
 
-// Resident blocks per CU of the render kernel (its brick-sparse variant when
-// sparse is set).
 template <int FMT, int MAXD, bool LIN>
-int occupancy_t(bool sparse) {
+hipError_t launch_render_t(const RenderArgs &a, int grid, hipStream_t s) {
+  const void *k = render_kernel<FMT, MAXD, LIN>(a.sched, a.c.slot != nullptr);
+  RenderArgs arg = a;
+  void *args[] = {&arg};
+  return hipLaunchKernel(k, dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+// Resident blocks per CU of the render kernel of a schedule and cache kind.
+template <int FMT, int MAXD, bool LIN>
+int occupancy_t(bool sparse, int sched) {
   int nb = 0;
-  hipError_t e;
-  if constexpr (!LIN) {
-    e = sparse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                     &nb, k_render_sparse<FMT, MAXD, sparse_waves(FMT, MAXD)>, kBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render<FMT, MAXD, false>,
-                                                              kBlock, 0);
-  } else {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_render<FMT, MAXD, true>, kBlock, 0);
-  }
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &nb, render_kernel<FMT, MAXD, LIN>(sched, sparse), kBlock, 0);
   return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 
 template <int FMT, bool LIN>
 hipError_t dispatch_maxd(int D, const RenderArgs *a, int grid, hipStream_t s, bool sparse,
-                         int *occ) {
-  if (D <= 4) return a ? launch_render_t<FMT, 4, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 4, LIN>(sparse), hipSuccess);
-  if (D <= 8) return a ? launch_render_t<FMT, 8, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 8, LIN>(sparse), hipSuccess);
-  return a ? launch_render_t<FMT, 16, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 16, LIN>(sparse), hipSuccess);
+                         int sched, int *occ) {
+  if (D <= 4) return a ? launch_render_t<FMT, 4, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 4, LIN>(sparse, sched), hipSuccess);
+  if (D <= 8) return a ? launch_render_t<FMT, 8, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 8, LIN>(sparse, sched), hipSuccess);
+  return a ? launch_render_t<FMT, 16, LIN>(*a, grid, s) : (*occ = occupancy_t<FMT, 16, LIN>(sparse, sched), hipSuccess);
 }
 
 template <int FMT>
 hipError_t dispatch_lin(bool lin, int D, const RenderArgs *a, int grid, hipStream_t s,
-                        bool sparse, int *occ) {
-  return lin ? dispatch_maxd<FMT, true>(D, a, grid, s, sparse, occ)
-             : dispatch_maxd<FMT, false>(D, a, grid, s, sparse, occ);
+                        bool sparse, int sched, int *occ) {
+  return lin ? dispatch_maxd<FMT, true>(D, a, grid, s, sparse, sched, occ)
+             : dispatch_maxd<FMT, false>(D, a, grid, s, sparse, sched, occ);
 }
 
 hipError_t dispatch(int fmt, bool lin, int D, const RenderArgs *a, int grid, hipStream_t s,
-                    bool sparse, int *occ) {
+                    bool sparse, int sched, int *occ) {
   switch (fmt) {
-    case 0: return dispatch_lin<0>(lin, D, a, grid, s, sparse, occ);
-    case 1: return dispatch_lin<1>(lin, D, a, grid, s, sparse, occ);
-    case 2: return dispatch_lin<2>(lin, D, a, grid, s, sparse, occ);
-    default: return dispatch_lin<3>(lin, D, a, grid, s, sparse, occ);
+    case 0: return dispatch_lin<0>(lin, D, a, grid, s, sparse, sched, occ);
+    case 1: return dispatch_lin<1>(lin, D, a, grid, s, sparse, sched, occ);
+    case 2: return dispatch_lin<2>(lin, D, a, grid, s, sparse, sched, occ);
+    default: return dispatch_lin<3>(lin, D, a, grid, s, sparse, sched, occ);
   }
 }
 
@@ -1062,14 +1293,14 @@ int render_step_occupancy(int fmt, bool lin, int D) {
   return occ;
 }
 
-int render_occupancy(int fmt, bool lin, int D, bool sparse) {
+int render_occupancy(int fmt, bool lin, int D, bool sparse, int sched) {
   int occ = 0;
-  (void)dispatch(fmt, lin, D, nullptr, 0, nullptr, sparse, &occ);
+  (void)dispatch(fmt, lin, D, nullptr, 0, nullptr, sparse, sched, &occ);
   return occ;
 }
 
 hipError_t launch_render(int fmt, bool lin, const RenderArgs &a, int grid, hipStream_t s) {
-  return dispatch(fmt, lin, a.c.D, &a, grid, s, a.c.slot != nullptr, nullptr);
+  return dispatch(fmt, lin, a.c.D, &a, grid, s, a.c.slot != nullptr, a.sched, nullptr);
 }
 
 namespace {

@@ -5,7 +5,9 @@ for every sample i the transmittance T_i is rebuilt from the explicit sum of
 sigma_j delta_j over the samples before i (no running product, no log-space
 state), the sample's voxel is found by testing every voxel's cell bounds, and
 the nearest direction cell by testing every (theta, phi) cell's bounds. The
-camera inverse is mpmath's matrix inverse.
+camera inverse is mpmath's matrix inverse. The bilinear direction lookup
+finds the four surrounding cell centres by search and blends them with weights
+from the distances to them.
 """
 from __future__ import annotations
 
@@ -29,11 +31,43 @@ def _cell_of(value, lo, hi, n, tie=0):
     return None
 
 
-TIE = mp.mpf(1) / 512  # cell boundaries 2^-9 voxel below the faces (reading R6b)
+def _bilinear_beta(beta, l, D, theta, phi):
+    """Bilinear blend of the direction cache between the four cell centres
+    around (theta, phi), found by searching the centres (theta_j = (j + 1/2)
+    pi / l, phi_m = (m + 1/2) 2 pi / l). Below the first or above the last
+    theta centre both rows are the edge row; phi wraps around (the centre
+    before phi_0 is phi_{l-1} - 2 pi)."""
+    th_c = [(j + mp.mpf(1) / 2) * mp.pi / l for j in range(l)]
+    ph_c = [(m + mp.mpf(1) / 2) * 2 * mp.pi / l for m in range(l)]
+    if theta <= th_c[0]:
+        j0 = j1 = 0
+        a = mp.mpf(0)
+    elif theta >= th_c[-1]:
+        j0 = j1 = l - 1
+        a = mp.mpf(0)
+    else:
+        j0 = max(j for j in range(l) if th_c[j] <= theta)
+        j1 = j0 + 1
+        a = (theta - th_c[j0]) / (th_c[j1] - th_c[j0])
+    if phi < ph_c[0]:
+        m0, m1, lo_c, hi_c = l - 1, 0, ph_c[-1] - 2 * mp.pi, ph_c[0]
+    elif phi >= ph_c[-1]:
+        m0, m1, lo_c, hi_c = l - 1, 0, ph_c[-1], ph_c[0] + 2 * mp.pi
+    else:
+        m0 = max(m for m in range(l) if ph_c[m] <= phi)
+        m1, lo_c, hi_c = m0 + 1, ph_c[m0], ph_c[m0 + 1]
+    b = (phi - lo_c) / (hi_c - lo_c)
+
+    def cell(j, m):
+        return [mp.mpf(float(beta[j][m][c])) for c in range(D)]
+
+    c00, c01, c10, c11 = cell(j0, m0), cell(j0, m1), cell(j1, m0), cell(j1, m1)
+    return [(1 - a) * (1 - b) * c00[c] + (1 - a) * b * c01[c] + a * (1 - b) * c10[c] +
+            a * b * c11[c] for c in range(D)]
 
 
 def render_pixel(sigma, u, beta, k, D, l, K, c2w, x, y, near, far, N, eps, bg,
-                 bbox=(-1, 1), in_box=False):
+                 bbox=(-1, 1), in_box=False, dir_linear=False):
     lo, hi = mp.mpf(bbox[0]), mp.mpf(bbox[1])
     Km = mp.matrix([[mp.mpf(float(K[r][c])) for c in range(3)] for r in range(3)])
     q = mp.inverse(Km) * mp.matrix([mp.mpf(x) + mp.mpf(1) / 2, mp.mpf(y) + mp.mpf(1) / 2, 1])
@@ -58,14 +92,17 @@ def render_pixel(sigma, u, beta, k, D, l, K, c2w, x, y, near, far, N, eps, bg,
     phi = mp.atan2(d[1], d[0])
     if phi < 0:
         phi += 2 * mp.pi
-    jt = _cell_of(theta, mp.mpf(0), mp.pi, l)
-    mphi = _cell_of(phi, mp.mpf(0), 2 * mp.pi, l) % l
-    b = [mp.mpf(float(beta[jt][mphi][c])) for c in range(D)]
+    if dir_linear:
+        b = _bilinear_beta(beta, l, D, theta, phi)
+    else:
+        jt = _cell_of(theta, mp.mpf(0), mp.pi, l)
+        mphi = _cell_of(phi, mp.mpf(0), 2 * mp.pi, l) % l
+        b = [mp.mpf(float(beta[jt][mphi][c])) for c in range(D)]
     sig, col = [], []
     for i in range(N):
         t = t0 + (i + mp.mpf(1) / 2) * delta
         p = [o[a] + t * d[a] for a in range(3)]
-        cells = [_cell_of(p[a], lo, hi, k, TIE) for a in range(3)]
+        cells = [_cell_of(p[a], lo, hi, k) for a in range(3)]
         if any(c is None for c in cells):
             sig.append(mp.mpf(0))
             col.append([mp.mpf(0)] * 3)

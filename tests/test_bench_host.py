@@ -80,3 +80,53 @@ def test_pmc_traffic_calibration(tmp_path):
     _counters(w, "WRITE_SIZE", [(2, ren, 200.0)])
     with pytest.raises(SystemExit):
         bench.pmc_traffic(f, w)
+
+
+def test_pmc_traffic_l2_hit_rate(tmp_path):
+    neg = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(x)"
+    ren = "void fnr::k_render<0, 8, false>(fnr::RenderArgs)"
+    f, w, t = str(tmp_path / "fetch"), str(tmp_path / "write"), str(tmp_path / "tcc")
+    _counters(f, "FETCH_SIZE", [(1, neg, 524288.0), (3, ren, 1000.0)])
+    _counters(w, "WRITE_SIZE", [(1, neg, 1048576.0), (2, ren, 200.0)])
+    os.makedirs(t, exist_ok=True)
+    with open(os.path.join(t, "run_counter_collection.csv"), "w", newline="") as fh:
+        wr = csv.writer(fh)
+        wr.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        wr.writerows([(4, ren, "TCC_HIT_sum", 30.0), (4, ren, "TCC_MISS_sum", 90.0),
+                      (5, neg, "TCC_HIT_sum", 1.0), (5, neg, "TCC_MISS_sum", 1.0)])
+    out = bench.pmc_traffic(f, w, t)
+    assert out["l2_hit_rate"] == pytest.approx(0.25)
+    assert (out["tcc_hit"], out["tcc_miss"]) == (30.0, 90.0)
+
+
+class _V:
+    def __init__(self, H, W):
+        self.H, self.W = H, W
+
+
+def test_launch_units_scale_to_every_view_of_the_launch():
+    """The oracle's per-ray averages over its sampled pixels are scaled to the
+    rays of the whole launch, whatever number of views the oracle finished."""
+    totals = dict(rays=1000, hit=700, occ_samples=28_000, pixels=2 * 640_000)
+    views = [_V(800, 800)] * 40
+    u = bench.launch_units(totals, views)
+    assert u["rays"] == 40 * 640_000
+    assert u["hit_rays"] == pytest.approx(0.7 * 40 * 640_000)
+    assert u["occ_samples"] == pytest.approx(28 * 40 * 640_000)
+    b = bench.alg_bytes(u, 100, 8)
+    assert b["records"] == pytest.approx(u["occ_samples"] * 100)
+    assert b["beta"] == pytest.approx(u["hit_rays"] * 128)
+    assert b["writes"] == pytest.approx(u["rays"] * 16)
+    assert b["total"] == pytest.approx(b["records"] + b["beta"] + b["writes"])
+    # uneven views: rays counted per view
+    u2 = bench.launch_units(dict(rays=10, hit=5, occ_samples=40, pixels=0),
+                            [_V(256, 256), _V(720, 1280)])
+    assert u2["rays"] == 256 * 256 + 720 * 1280
+    assert u2["occ_samples"] == pytest.approx(4 * u2["rays"])
+
+
+def test_host_cpu_description():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and 1 <= h["usable_cpus"] <= h["nproc"]
+    assert isinstance(h["cpu_model"], str) and h["cpu_model"]
+    assert bench.oracle_threads() >= 1

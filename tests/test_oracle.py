@@ -43,21 +43,26 @@ def _tiny_random(seed, k=4, D=3, l=4, density=0.6):
 
 # ----------------------------------------------------------------- Eq. 1 brute force
 
-@pytest.mark.parametrize("seed,in_box,eps", [(0, False, 0.0), (1, True, 0.0), (2, False, 0.3),
-                                             (3, True, 0.05)])
-def test_brute_force_eq1(seed, in_box, eps):
+@pytest.mark.parametrize("seed,in_box,eps,dir_linear", [
+    (0, False, 0.0, False), (1, True, 0.0, False), (2, False, 0.3, False), (3, True, 0.05, False),
+    (4, False, 0.0, True), (5, True, 0.05, True), (6, False, 0.0, True)])
+def test_brute_force_eq1(seed, in_box, eps, dir_linear):
     """Literal Eq. 1 in 50 digits (O(N^2) transmittance sums, voxel and direction
-    cells found by search) agrees with the oracle to 1e-12 on a tiny scene."""
+    cells found by search, bilinear direction weights from the distances to the
+    surrounding cell centres) agrees with the oracle to 1e-12 on a tiny scene."""
     k, D, l, N = 4, 3, 4, 16
     sigma, u, beta = _tiny_random(seed, k, D, l)
-    sc = oracle.Scene(beta, sigma, u, pos_linear=False, dir_linear=False, in_box=in_box,
+    sc = oracle.Scene(beta, sigma, u, pos_linear=False, dir_linear=dir_linear, in_box=in_box,
                       bg=(0.2, 0.5, 0.9))
-    v = synth.orbit_view(2.2, 0.3 + seed, 0.35, 3, 3, 1.0, 3.4, f=2.0)
+    # seed 6 looks down at the scene (theta near pi, inside the last theta row's clamp)
+    el = -1.3 if seed == 6 else 0.35
+    v = synth.orbit_view(2.2, 0.3 + seed, el, 3, 3, 1.0, 3.4, f=2.0)
     res = oracle.render(sc, v.K, v.c2w, 3, 3, v.near, v.far, N, eps, tol=None)
     for q in range(9):
         x, y = q % 3, q // 3
         ref = brute_eq1.render_pixel(sigma, u, beta, k, D, l, v.K, v.c2w, x, y, v.near, v.far,
-                                     N, eps, (0.2, 0.5, 0.9), in_box=in_box)
+                                     N, eps, (0.2, 0.5, 0.9), in_box=in_box,
+                                     dir_linear=dir_linear)
         np.testing.assert_allclose(res["rgba"][q], [float(r) for r in ref], rtol=0, atol=1e-12)
 
 
@@ -135,13 +140,13 @@ def test_nearest_lookup_matches_cell_search():
     rng = np.random.default_rng(1)
     pts = rng.uniform(-1.2, 1.2, (500, 3))
     pts[:20] = rng.integers(0, k + 1, (20, 3)) * (2.0 / k) - 1.0  # exactly on faces
-    # just below faces: within 2^-9 voxel (upper cell) and beyond it (lower cell)
-    pts[20:40] = rng.integers(1, k, (20, 3)) * (2.0 / k) - 1.0 - 0.5 / 512 * (2.0 / k)
-    pts[40:60] = rng.integers(1, k, (20, 3)) * (2.0 / k) - 1.0 - 1.5 / 512 * (2.0 / k)
+    # just below faces (the lower cell) by 1e-6 and 1e-4 voxel
+    pts[20:40] = rng.integers(1, k, (20, 3)) * (2.0 / k) - 1.0 - 1e-6 * (2.0 / k)
+    pts[40:60] = rng.integers(1, k, (20, 3)) * (2.0 / k) - 1.0 - 1e-4 * (2.0 / k)
     sig, uu = oracle.lookup_pos(sc, pts)
     for p, s, uv in zip(pts, sig, uu):
-        cells = [brute_eq1._cell_of(Fraction(float(x)), Fraction(-1), Fraction(1), k,
-                                    Fraction(1, 512)) for x in p]
+        cells = [brute_eq1._cell_of(Fraction(float(x)), Fraction(-1), Fraction(1), k)
+                 for x in p]
         if any(c is None for c in cells):
             assert s == 0 and np.all(uv == 0)
         else:
@@ -197,6 +202,152 @@ def test_bilinear_direction_lookup():
                        np.zeros((2, 2, 2, D, 3), np.float32))
     np.testing.assert_allclose(oracle.lookup_dir(sc2, dirs), np.tile(const[0, 0], (200, 1)),
                                atol=1e-7)
+
+
+def test_bilinear_direction_lookup_theta_axis():
+    """The theta half of the bilinear lookup (readings R4, R5): a field
+    bilinear in (theta, phi) at the cell centres, f = a + b theta + c phi +
+    e theta phi, is reproduced exactly between the first and last centres
+    (both axes and the cross term); above the last theta centre and below the
+    first the lookup clamps to the edge row, so it is constant in theta there."""
+    l, D = 12, 2
+    th_c = (np.arange(l) + 0.5) * math.pi / l
+    ph_c = (np.arange(l) + 0.5) * 2 * math.pi / l
+    coef = np.array([[0.3, 0.1, -0.05, 0.02], [0.6, -0.08, 0.03, -0.01]])
+
+    def field(th, ph):
+        th, ph = np.asarray(th)[..., None], np.asarray(ph)[..., None]
+        return coef[:, 0] + coef[:, 1] * th + coef[:, 2] * ph + coef[:, 3] * th * ph
+
+    TH, PH = np.meshgrid(th_c, ph_c, indexing="ij")
+    beta = field(TH, PH).astype(np.float32)
+    sc = oracle.Scene(beta, np.zeros((2, 2, 2), np.float32),
+                      np.zeros((2, 2, 2, D, 3), np.float32))
+
+    def dirs_of(th, ph):
+        return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1)
+
+    rng = np.random.default_rng(17)
+    ph = rng.uniform(ph_c[0], ph_c[-1], 400)
+    th = rng.uniform(th_c[0], th_c[-1], 400)
+    # float32 storage of beta: about 6e-8 relative
+    np.testing.assert_allclose(oracle.lookup_dir(sc, dirs_of(th, ph)), field(th, ph), atol=1e-6)
+    th_lo = rng.uniform(1e-3, th_c[0], 100)
+    np.testing.assert_allclose(oracle.lookup_dir(sc, dirs_of(th_lo, ph[:100])),
+                               field(np.full(100, th_c[0]), ph[:100]), atol=1e-6)
+    th_hi = rng.uniform(th_c[-1], math.pi - 1e-3, 100)
+    np.testing.assert_allclose(oracle.lookup_dir(sc, dirs_of(th_hi, ph[:100])),
+                               field(np.full(100, th_c[-1]), ph[:100]), atol=1e-6)
+    # at a theta centre the lookup is that row's phi interpolation, exactly
+    j = 5
+    b = oracle.lookup_dir(sc, dirs_of(np.full(50, th_c[j]), ph[:50]))
+    np.testing.assert_allclose(b, field(np.full(50, th_c[j]), ph[:50]), atol=1e-6)
+
+
+# ----------------------------------------------------------------- counts behind the byte count
+
+def _counts_scene(k, ob, occupied, sig):
+    """k^3 grid, one brick of edge ob set: voxels listed in ``occupied`` get
+    density sig (all voxels of the brick when occupied is a brick index)."""
+    sigma = np.zeros((k, k, k), np.float32)
+    u = np.zeros((k, k, k, 1, 3), np.float32)
+    for (x, y, z) in occupied:
+        sigma[z, y, x] = sig
+        u[z, y, x, 0] = [0.2, 0.4, 0.6]
+    beta = np.ones((4, 4, 1), np.float32)
+    return oracle.Scene(beta, sigma, u, dir_linear=False, bg=BG, occ_brick=ob)
+
+
+def test_occupied_sample_count_closed_form():
+    """Samples in occupied bricks before the stop (the count behind the
+    algorithmic bytes of the render): k = 16, bricks of 4 voxels, an axis ray
+    along +x through one occupied brick. Without termination the count is the
+    number of sample midpoints inside the brick's x extent (exact rationals),
+    whatever the voxel densities inside it; with termination it stops after
+    n = min(m, floor(ln(1/eps) / (sigma delta)) + 1) samples of a brick filled
+    with sigma, and samples after the stop are not counted."""
+    k, ob = 16, 4
+    h = Fraction(2, k)
+    y0 = -1 + (5 + Fraction(3, 10)) * h   # voxel row y = 5 (brick 1)
+    z0 = -1 + (13 + Fraction(6, 10)) * h  # z = 13 (brick 3)
+    K, c2w = _one_ray_view((-3.0, float(y0), float(z0)), (0.0, float(y0), float(z0)),
+                           up=(0.0, 0.0, 1.0))
+    near, far, N = Fraction(1), Fraction(5), 100
+    delta = (far - near) / N
+    xs = [-3 + near + (i + Fraction(1, 2)) * delta for i in range(N)]
+    a, b = -1 + 8 * h, -1 + 12 * h        # brick bx = 2: voxels 8..11
+    m = sum(1 for x in xs if a <= x < b)
+    in_box = sum(1 for x in xs if -1 <= x <= 1)
+    one = sum(1 for x in xs if -1 + 9 * h <= x < -1 + 10 * h)
+    assert (m, in_box, one) == (12, 50, 3)
+    # one voxel of the brick has density: every sample in the brick counts
+    sc = _counts_scene(k, ob, [(9, 5, 13)], 7.0)
+    c = oracle.render(sc, K, c2w, 1, 1, float(near), float(far), N, 0.0, tol=None)["counts"]
+    assert (c["rays"], c["hit"], c["samples"], c["occ_samples"], c["nonzero_samples"]) == \
+        (1, 1, in_box, m, one)
+    # the whole brick filled with sigma = 40: sigma delta = 1.6, eps = 1e-2
+    sig, eps = 40.0, 1e-2
+    brick = [(x, y, z) for x in range(8, 12) for y in range(4, 8) for z in range(12, 16)]
+    sc = _counts_scene(k, ob, brick, sig)
+    c = oracle.render(sc, K, c2w, 1, 1, float(near), float(far), N, eps, tol=None)["counts"]
+    n = min(m, math.floor(math.log(1 / eps) / (sig * float(delta))) + 1)
+    assert n == 3
+    first = sum(1 for x in xs if -1 <= x < a)  # in-box samples before the brick
+    assert (c["occ_samples"], c["nonzero_samples"], c["samples"]) == (n, n, first + n)
+    # a stop point inside the band of reading R8 (optical depth 4.8 against
+    # ln(1/eps) = 4.7995): the oracle also evaluates the sample after it, as
+    # an admissible variant, but the counts stop with the primary result
+    eps_b = math.exp(-4.7995)
+    res = oracle.render(sc, K, c2w, 1, 1, float(near), float(far), N, eps_b,
+                        tol=oracle.DEFAULT_TOL)
+    assert res["ncand"][0] >= 2  # (the direction lookup of this axis ray is on cell borders too)
+    assert res["counts"]["occ_samples"] == min(m, math.floor(4.7995 / (sig * float(delta))) + 1)
+    # no occupancy grid given: nothing is counted as occupied
+    sc = oracle.Scene(np.ones((4, 4, 1), np.float32), sc.sigma, sc.u, dir_linear=False)
+    c = oracle.render(sc, K, c2w, 1, 1, float(near), float(far), N, eps, tol=None)["counts"]
+    assert c["occ_samples"] == 0
+
+
+def test_hit_ray_count_closed_form():
+    """Rays whose interval is non-empty: a camera on the -x axis looking at
+    the box face-on sees the box as its front face (distance 2, half-width 1),
+    so a pixel's ray hits exactly when |x + 1/2 - cx| < f/2 and
+    |y + 1/2 - cy| < f/2 (no pixel lies on the silhouette with f = 12.5). In
+    NEAR_FAR mode every ray has the interval [near, far]."""
+    W = H = 21
+    f, cx = 12.5, 10.5
+    K = np.array([[f, 0, cx], [0, f, cx], [0, 0, 1.0]])
+    c2w = synth.look_at((-3.0, 0.0, 0.0), (0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0))
+    n_axis = sum(1 for x in range(W) if abs(x + 0.5 - cx) < f / 2)
+    assert n_axis == 13
+    sc = _const_scene(8, 1, 4, 2.0, [[0.1, 0.2, 0.3]], [1.0], in_box=True)
+    c = oracle.render(sc, K, c2w, H, W, 0.5, 10.0, 8, 0.0, tol=None)["counts"]
+    assert (c["rays"], c["hit"]) == (W * H, n_axis ** 2)
+    sc = _const_scene(8, 1, 4, 2.0, [[0.1, 0.2, 0.3]], [1.0], in_box=False)
+    c = oracle.render(sc, K, c2w, H, W, 0.5, 10.0, 8, 0.0, tol=None)["counts"]
+    assert (c["rays"], c["hit"]) == (W * H, W * H)
+
+
+def test_threaded_bands_equal_single_thread():
+    """The oracle split into row bands over several threads (the all-core CPU
+    baseline) gives bitwise the single-threaded results and the same counts."""
+    sig, u, beta, _ = synth.scene_arrays(synth.SceneSpec(k=32, D=4, l=8, n_ellipsoids=5,
+                                                         seed=12))
+    sc = oracle.Scene(beta, sig, u, in_box=True, occ_brick=8)
+    v = synth.orbit_view(3.0, 0.9, 0.3, 23, 19, 2.0, 4.0)
+    one = oracle.render(sc, v.K, v.c2w, 19, 23, 2.0, 4.0, 48, 1e-4)
+    pix = np.sort(np.random.default_rng(2).choice(19 * 23, 200, replace=False))
+    one_p = oracle.render(sc, v.K, v.c2w, 19, 23, 2.0, 4.0, 48, 1e-4, pix=pix)
+    for threads in (2, 5, 8):
+        many = oracle.render(sc, v.K, v.c2w, 19, 23, 2.0, 4.0, 48, 1e-4, threads=threads)
+        for key in ("rgba", "cand", "ncand", "flags"):
+            assert np.array_equal(one[key], many[key]), key
+        assert one["counts"] == many["counts"]
+        many_p = oracle.render(sc, v.K, v.c2w, 19, 23, 2.0, 4.0, 48, 1e-4, pix=pix,
+                               threads=threads)
+        assert np.array_equal(one_p["rgba"], many_p["rgba"])
+        assert one_p["counts"] == many_p["counts"]
+    assert one["counts"]["occ_samples"] > 0
 
 
 # ----------------------------------------------------------------- rays and intervals
@@ -353,8 +504,9 @@ def test_brick_sparse_source_equals_dense():
 
 def test_cell_boundary_ambiguity_and_face_ties():
     """A sample exactly on a voxel face takes the upper cell (reading R6,
-    R6b); a sample exactly on a cell boundary (2^-9 voxel below a face) admits
-    both voxels (reading R13) and the oracle enumerates the variants."""
+    R6b) with no alternative; a sample 2e-4 voxel below a face lies in the lower
+    cell but within the band of reading R13, so both voxels are admissible and
+    the oracle enumerates the variants."""
     k, D = 4, 1
     sigma = np.zeros((k, k, k), np.float32)
     u = np.zeros((k, k, k, D, 3), np.float32)
@@ -369,22 +521,24 @@ def test_cell_boundary_ambiguity_and_face_ties():
     res = oracle.render(sc, K, c2w, 1, 1, 2.0, 4.0, 8, 0.0)
     assert res["ncand"][0] == 1  # x exactly on the face between voxels 1 and 2
     assert res["rgba"][0, 0] == 0 and res["rgba"][0, 1] > 0  # upper cell: voxel 2
-    xb = -(2.0 / k) / 512  # the cell boundary below that face
+    xb = -(2.0 / k) * 2e-4  # just below that face
     K, c2w = _one_ray_view((xb, -3.0, -0.25), (xb, 0.0, -0.25), up=(0.0, 0.0, 1.0))
     res = oracle.render(sc, K, c2w, 1, 1, 2.0, 4.0, 8, 0.0)
     assert res["ncand"][0] == 4 and res["flags"][0] & oracle.AMBIG
     first, last = res["cand"][0, 0], res["cand"][0, 3]
-    assert first[0] == 0 and first[1] > 0   # primary: both samples in the upper cell
-    assert last[0] > 0 and last[1] == 0     # both in the lower cell
+    assert first[0] > 0 and first[1] == 0   # primary: both samples in the lower cell
+    assert last[0] == 0 and last[1] > 0     # both in the upper cell
     np.testing.assert_array_equal(res["rgba"][0], first)
+    xf = -(2.0 / k) * 2e-3  # outside the band: one result
+    K, c2w = _one_ray_view((xf, -3.0, -0.25), (xf, 0.0, -0.25), up=(0.0, 0.0, 1.0))
+    assert oracle.render(sc, K, c2w, 1, 1, 2.0, 4.0, 8, 0.0)["ncand"][0] == 1
 
 
 def test_commensurate_lattice_has_no_face_ties():
     """With k/N = 4 voxels per sample (paper-scale ratio, here k=64, N=16 inside
     the box) rays crossing the box between opposite faces put every sample on
-    a voxel face; with the cell boundaries 2^-9 voxel below the faces (reading
-    R6b) none of these samples is ambiguous, and the result equals the one with
-    the samples nudged into the upper cells."""
+    a voxel face; such samples take the upper cell (readings R6, R6b) and are
+    not ambiguous, so no pixel overflows the enumeration."""
     spec = synth.paper_scene_spec(k=64)
     p = synth.draw(spec)
     slot, ss, su = synth.brick_sparse(p, 8)
@@ -430,17 +584,16 @@ def test_voxel_traversal_homogeneous_exact(k, eye, target, chord):
 
 def test_voxel_traversal_termination_on_an_axis_ray():
     """Axis ray (along -x) through a homogeneous box of k voxels: the pieces
-    are the cells between the boundaries at grid coordinates i - 2^-9 (R6b),
-    in grid units 1 + 2^-9 (the first piece met, cell k-1), then 1, ..., 1,
-    then 1 - 2^-9; the stop rule (stop before a piece once the optical depth
-    exceeds ln(1/eps)) keeps the first n pieces, L their total length, and
+    are the k cells between the voxel faces, each one voxel long; the stop
+    rule (stop before a piece once the optical depth exceeds ln(1/eps)) keeps
+    the first n pieces, L their total length, and
     C = c (1 - exp(-sigma L)) + exp(-sigma L) bg."""
     k, D, sig, eps = 20, 1, 9.0, 1e-2
-    h, tie = 2.0 / k, 1.0 / 512.0
+    h = 2.0 / k
     sc = _const_scene(k, D, 4, sig, [[0.2, 0.5, -0.7]], [1.0], bg=BG)
     K, c2w = _one_ray_view((3.0, 0.013, -0.021), (0.0, 0.013, -0.021))
     res = oracle.render(sc, K, c2w, 1, 1, 0.0, 100.0, 0, eps, tol=None)
-    pieces = [(1 + tie) * h] + [h] * (k - 2) + [(1 - tie) * h]
+    pieces = [h] * k
     L, lim = 0.0, math.log(1 / eps)
     for p in pieces:
         if sig * L > lim:
@@ -468,8 +621,7 @@ def _slab_length(o, d, lo, hi):
 
 def test_voxel_traversal_single_voxel_slab_length():
     """One occupied interior voxel, rays in many directions: the piece inside
-    the voxel has the length of the ray clipped to the voxel's cell (its faces
-    2^-9 voxel below the grid planes, R6b), so
+    the voxel has the length of the ray clipped to the voxel's cell, so
     C = c (1 - exp(-sigma l)) + exp(-sigma l) bg with l from a slab test."""
     k, D = 6, 1
     vx, vy, vz = 2, 3, 3
@@ -479,8 +631,8 @@ def test_voxel_traversal_single_voxel_slab_length():
     u[vz, vy, vx, 0] = [0.9, -0.3, 0.4]
     beta = np.ones((4, 4, D), np.float32)
     sc = oracle.Scene(beta, sigma, u, dir_linear=False, bg=BG)
-    h, tie = 2.0 / k, 1.0 / 512.0
-    lo = np.array([-1 + (vx - tie) * h, -1 + (vy - tie) * h, -1 + (vz - tie) * h])
+    h = 2.0 / k
+    lo = np.array([-1 + vx * h, -1 + vy * h, -1 + vz * h])
     centre = lo + h / 2
     col = np.array([0.9, -0.3, 0.4], np.float32).astype(np.float64)
     rng = np.random.default_rng(4)

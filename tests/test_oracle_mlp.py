@@ -130,12 +130,12 @@ def test_sample_points():
     np.testing.assert_allclose(p, [[-0.75, -0.25, 0.75]], rtol=0, atol=1e-15)
     p = mlp.voxel_centres(5, (0, -2, 1), (1, 2, 3), [[2, 0, 4]])
     np.testing.assert_allclose(p, [[0.5, -1.6, 2.8]], atol=1e-15)
-    # the voxel index of a centre under the renderer's nearest rule (cell
-    # boundaries 2^-9 voxel below the faces) is the voxel itself
+    # the voxel index of a centre under the nearest rule (the cell that holds
+    # the point) is the voxel itself
     k = 7
     idx = mlp.slab_indices(k, 0, k)
     g = (mlp.voxel_centres(k, (-1, -1, -1), (1, 1, 1), idx) + 1) / 2 * k
-    assert np.array_equal(np.minimum(np.floor(g + 2.0 ** -9), k - 1).astype(int), idx)
+    assert np.array_equal(np.minimum(np.floor(g), k - 1).astype(int), idx)
     d = mlp.direction_centres(2, [[0, 0]])
     np.testing.assert_allclose(d, [[0.0, math.sqrt(2) / 2, math.sqrt(2) / 2]], atol=1e-15)
     l = 9

@@ -51,7 +51,13 @@ def test_config1_fp32_parity():
     print(f"config1 f32: max err {err:.2e}, ambiguous {res['counts']['ambiguous_pixels']}, "
           f"unchecked {unchecked}")
     assert failing == 0
-    assert G.psnr(gpu, res["rgba"]) > 60
+    # against the admissible result each pixel matched; against the oracle's
+    # primary result it is lower where the kernel took the other admissible
+    # voxel of a sample within FP32 rounding of a face (reading R13)
+    p_matched, p_primary = G.psnr(gpu, G.matched(gpu, res)), G.psnr(gpu, res["rgba"])
+    print(f"PSNR {p_matched:.1f} dB against the matched admissible results, "
+          f"{p_primary:.1f} dB against the primary ones")
+    assert p_matched > 100 and p_primary > 50
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16", "fp8"])
@@ -76,7 +82,7 @@ def test_config1_precision_cost():
     for storage in ("f16", "bf16", "fp8"):
         gpu = G.render_gpu(G.make_cache(sig, u, beta, storage=storage), v, 128, 1e-4)
         err, _ = oracle.matches(gpu, res, 1.0)
-        out[storage] = (float(err.max()), G.psnr(gpu, res["rgba"]))
+        out[storage] = (float(err.max()), G.psnr(gpu, G.matched(gpu, res)))
     print("precision cost (max-abs, PSNR):", out)
     assert out["f16"][0] <= G.F16_COST_TOL
     assert out["fp8"][1] >= G.FP8_MIN_PSNR
@@ -129,7 +135,7 @@ def test_debug_lookup_matches_oracle(pos_linear, dir_linear):
     rng = np.random.default_rng(4)
     pts = rng.uniform(-1.1, 1.1, (4000, 3))
     # stay away from cell boundaries (nearest) so FP32 and FP64 pick the same voxel
-    g = (pts + 1) * 8 + oracle.TIE
+    g = (pts + 1) * 8
     keep = np.all(np.abs(g - np.round(g)) > 1e-3, axis=1)
     pts = pts[keep]
     dirs = rng.standard_normal((3000, 3))
