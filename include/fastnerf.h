@@ -164,8 +164,24 @@ fastnerf_status fastnerf_render_batch(fastnerf_cache cache, int32_t nviews, cons
                                       const float *near, const float *far, int32_t N, float eps,
                                       float *const *out, hipStream_t stream);
 
+/* fastnerf_render without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, checks, result and asynchrony as
+ * fastnerf_render (images up to 65536 x 65536; N = 0 allowed); out is the
+ * caller's device buffer. Its only scratch is the render's tile-queue
+ * counters, 4 KiB in a fixed array in the library's device memory (one copy
+ * per device, held until the process ends, its address looked up on the
+ * device's first call), whatever the image size; each call clears them on
+ * `stream` with a small kernel before the render. Every call on a device
+ * shares that array: calls that overlap on one device (on different streams,
+ * or from several host threads) race and must be ordered by the caller. */
+fastnerf_status fastnerf_render_noalloc(fastnerf_cache cache, const float K[9],
+                                        const float c2w[12], int32_t H, int32_t W, float near,
+                                        float far, int32_t N, float eps, float *out,
+                                        hipStream_t stream);
+
 /* Scheduling of the fixed-N render launches (fastnerf_render,
- * fastnerf_render_batch), process-wide. TILES: each
+ * fastnerf_render_batch, fastnerf_render_noalloc), process-wide. TILES: each
  * wave renders one 8x8 pixel tile at a time (one ray per lane) and takes the
  * next tile when all of its rays have stopped. REFILL: the wave-level ray
  * queue -- after each window of samples the wave takes a ballot of its live

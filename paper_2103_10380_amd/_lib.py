@@ -66,6 +66,8 @@ SYMBOLS = {
     "fastnerf_render": (_i32, [_vp, _pf, _pf, _i32, _i32, _f32, _f32, _i32, _f32, _vp, _vp]),
     "fastnerf_render_batch": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _vp,
                                      _vp]),
+    "fastnerf_render_noalloc": (_i32, [_vp, _pf, _pf, _i32, _i32, _f32, _f32, _i32, _f32, _vp,
+                                       _vp]),
     "fastnerf_set_schedule": (_i32, [_i32]),
     "fastnerf_get_schedule": (_i32, []),
     "fastnerf_debug_lookup": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -252,6 +254,18 @@ def render(cache: Cache, K, c2w, H, W, near, far, N, eps, out=None, stream=None)
     c_, cp = _arr9(c2w, 12)
     check(lib().fastnerf_render(cache.handle, kp, cp, H, W, near, far, N, eps, _ptr(out),
                                 _stream(stream)))
+    return out
+
+
+def render_noalloc(cache: Cache, K, c2w, H, W, near, far, N, eps, out, stream=None):
+    """fastnerf_render_noalloc: renders one view into the caller's [H, W, 4] FP32
+    device tensor with no allocation in the library (asynchronous)."""
+    if tuple(out.shape) != (H, W, 4) or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [H, W, 4] device tensor")
+    k_, kp = _arr9(K, 9)
+    c_, cp = _arr9(c2w, 12)
+    check(lib().fastnerf_render_noalloc(cache.handle, kp, cp, H, W, near, far, N, eps,
+                                        _ptr(out), _stream(stream)))
     return out
 
 

@@ -703,6 +703,64 @@ extern "C" fastnerf_status fastnerf_render(fastnerf_cache c, const float K[9],
   return enqueue_render(c, a, tiles, ss->counter, s);
 }
 
+// ------------------------------------------------------------------ allocation-free render
+
+// Tile-queue counters of fastnerf_render_noalloc: a fixed array in the
+// library's own device memory, one copy per device (4 KiB), held until the
+// process ends. In host code `scratch` names a host-side stand-in, not device
+// memory: the kernels get the device address found once per device below.
+static __device__ __align__(256) unsigned scratch[fnr::kQueueCounters];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned *g_scratch_addr[kMaxDevices];  // device address of `scratch`, per device
+
+// Device address of the current device's `scratch`, looked up on the device's
+// first call (with that device current) and kept.
+static fastnerf_status scratch_address(unsigned **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FASTNERF_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "address of the render scratch counters");
+    g_scratch_addr[dev] = static_cast<unsigned *>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return FASTNERF_OK;
+}
+
+extern "C" fastnerf_status fastnerf_render_noalloc(fastnerf_cache c, const float K[9],
+                                                   const float c2w[12], int32_t H, int32_t W,
+                                                   float near_, float far_, int32_t N, float eps,
+                                                   float *out, hipStream_t s) {
+  if (!c) return fail(FASTNERF_EINVAL, "null cache");
+  if (!c->finalized) return fail(FASTNERF_EINVAL, "cache not finalized");
+  fastnerf_status st = check_view(K, c2w, H, W, near_, far_, out);
+  if (st == FASTNERF_OK) st = check_render_params(N, eps);
+  if (st == FASTNERF_OK) st = check_voxel_mode(c, N);
+  if (st != FASTNERF_OK) return st;
+  unsigned *ctr = nullptr;
+  st = scratch_address(&ctr);
+  if (st != FASTNERF_OK) return st;
+  // the counters start at zero on this stream whatever an earlier call left
+  const hipError_t e = launch_fill_u32(ctr, kQueueCounters, 0u, s);
+  if (e != hipSuccess) return hip_fail(e, "scratch counter clear");
+  RenderArgs a;
+  memset(&a, 0, sizeof a);
+  a.c = dev_cache(c);
+  make_view(c, K, c2w, H, W, near_, far_, out, 0, &a.v0);
+  a.v0.N = N;
+  a.v0.lim = eps_limit(eps);
+  a.views = nullptr;
+  a.nviews = 1;
+  a.vox = N == 0;
+  const int tiles = ((W + 7) / 8) * ((H + 7) / 8);
+  return enqueue_render(c, a, tiles, ctr, s);
+}
+
 extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nviews,
                                                  const float *K, const float *c2w,
                                                  const int32_t *H, const int32_t *W,

@@ -19,6 +19,7 @@ int render_vox_occupancy(int fmt, int D);
 hipError_t launch_render_vox(int fmt, const RenderArgs &a, int grid, hipStream_t s);
 hipError_t launch_absmax(const float *sigma, const float *u, int64_t nvox, int D, unsigned *amax,
                          hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
 hipError_t launch_make_scales(const unsigned *amax, int nch, float *scales, hipStream_t s);
 hipError_t launch_pack(int fmt, const float *sigma, const float *u, int z0, int nz,
                        const DevCache &c, hipStream_t s);

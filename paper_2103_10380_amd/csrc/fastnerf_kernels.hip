@@ -951,6 +951,12 @@ __global__ void k_absmax(const float *__restrict__ sigma, const float *__restric
   }
 }
 
+// Sets n words to v (queue counters that must start at zero; a kernel rather
+// than a memset so that a captured graph replays it reliably).
+__global__ void k_fill_u32(unsigned *p, int n, unsigned v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
 __global__ void k_make_scales(const unsigned *amax, int nch, float *scales) {
   const int j = threadIdx.x;
   if (j < nch) {
@@ -1354,6 +1360,11 @@ hipError_t launch_absmax(const float *sigma, const float *u, int64_t nvox, int D
   int64_t blocks = (nvox + kBlock - 1) / kBlock;
   const int grid = (int)(blocks < 1024 ? (blocks < 1 ? 1 : blocks) : 1024);
   hipLaunchKernelGGL(k_absmax, dim3(grid), dim3(kBlock), 0, s, sigma, u, nvox, D, amax);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p, n, v);
   return hipGetLastError();
 }
 
