@@ -58,9 +58,10 @@ def storage_of(name):
     return (name[:-1], True) if name.endswith("s") else (name, False)
 
 
-def build_caches(spec, storages, want_sparse, device):
+def build_caches(spec, storages, want_sparse, device, brick=8):
     """Generates the scene slab by slab on the GPU and uploads it to one cache
-    per storage format; optionally keeps a brick-sparse host copy."""
+    per storage format; optionally keeps a brick-sparse host copy. `brick` is
+    the occupancy brick edge of the dense caches (brick-sparse ones use 8)."""
     import paper_2103_10380_amd as fn
     import synth
     p = synth.draw(spec)
@@ -68,8 +69,9 @@ def build_caches(spec, storages, want_sparse, device):
     caches = {}
     for st in storages:
         base, is_sparse = storage_of(st)
-        desc = fn.make_desc(spec.k, spec.D, spec.l, storage=base, brick=8,
-                            sample_mode=fn.IN_BOX, sparse=is_sparse)
+        desc = fn.make_desc(spec.k, spec.D, spec.l, storage=base,
+                            brick=8 if is_sparse else brick, sample_mode=fn.IN_BOX,
+                            sparse=is_sparse)
         caches[st] = fn.Cache.create_empty(desc, beta)
     k, sb = spec.k, 8
     # FP8 scales and the stored bricks of sparse caches need the whole cache first
@@ -178,7 +180,7 @@ def oracle_threads():
 
 
 def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs, seed=11,
-                  threads=1):
+                  threads=1, brick=8):
     """The FP64 oracle on random pixels of every view, single-threaded (stops
     at the time budget after completing a whole view) and, on the same pixels,
     split into row bands over `threads` threads (bitwise the same results,
@@ -188,7 +190,7 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs
     import oracle
     import torch
     sb, slot, ss, su = sparse
-    sc = oracle.Scene(beta, k=spec.k, sparse=(sb, slot, ss, su), in_box=True, occ_brick=8)
+    sc = oracle.Scene(beta, k=spec.k, sparse=(sb, slot, ss, su), in_box=True, occ_brick=brick)
     rng = np.random.default_rng(seed)
     rays, t_cpu, t_mt, nviews = 0, 0.0, 0.0, 0
     totals = dict(hit=0, occ_samples=0, rays=0, pixels=0)
@@ -215,13 +217,18 @@ def oracle_sample(beta, sparse, spec, views, N, eps, pix_per_view, seconds, outs
         totals["pixels"] += v.H * v.W
         idx = torch.as_tensor(pix, device=outs["f32"][vi].device)
         g = outs["f32"][vi].reshape(-1, 4)[idx].cpu().numpy().astype(np.float64)
+        # a pixel with too many ambiguous lookups to enumerate is checked
+        # against the oracle's interval bounds of all its admissible results
         err, ok = oracle.matches(g, r, 1e-4)
         unchecked = (r["flags"] & oracle.UNCHECKED) != 0
-        f32["fails"] += int((~ok & ~unchecked).sum())
+        f32["fails"] += int((~ok).sum())
         f32["checked"] += int((~unchecked).sum())
         f32["unchecked"] += int(unchecked.sum())
         if (~unchecked).any():
             f32["worst"] = max(f32["worst"], float(err[~unchecked].max()))
+        if unchecked.any():
+            wdt = (r["env"][unchecked, 1] - r["env"][unchecked, 0]).max(axis=1)
+            f32["bound_width_max"] = max(f32.get("bound_width_max", 0.0), float(wdt.max()))
         # the other formats over the same checked pixels (an unchecked pixel
         # has no admissible oracle result to compare with)
         chk = ~unchecked
@@ -549,16 +556,17 @@ def serve_offline(fn, caches, n_req, n_warm, seed=3, N=192, eps=1e-4, chunk=32):
             "frames_per_s": round(n_req / el, 1), "mrays_per_s": round(rays / el / 1e6, 1)}
 
 
-def serve_poisson(fn, caches, lam, n_req, n_warm, seed=3, N=192, eps=1e-4):
+def serve_poisson(fn, caches, lam, n_req, n_warm, seed=3, N=192, eps=1e-4, arena_bytes=0):
     """Poisson arrivals at lam requests/s over the resident caches: each request
     draws a scene, a resolution from SERVE_RES and a pose (r U[3,5], az U[0,2pi),
     el U[-1,1]); a waiter thread collects results in submission order.
-    Latency is the server's (submission to completion)."""
+    Latency is the server's (submission to completion). arena_bytes = 0: the
+    server admits requests against a quarter of the free device memory."""
     import threading
     import queue
     import synth
     rng = np.random.default_rng(seed)
-    srv = fn.Server(caches, arena_bytes=4 << 30, max_inflight=32)
+    srv = fn.Server(caches, arena_bytes=arena_bytes, max_inflight=32)
     q = queue.Queue()
     lat, rays_done, done_t = [], [0], [0.0]
 
@@ -763,6 +771,9 @@ def main():
                     help="print the render kernel's calibrated HBM bytes per launch (JSON) "
                          "from FETCH_SIZE and WRITE_SIZE runs made with --calibrate-copy "
                          "(FETCH_DIR WRITE_DIR [TCC_DIR]; the third adds the L2 hit rate)")
+    ap.add_argument("--brick", type=int, default=8,
+                    help="occupancy brick edge of the dense caches (the workload's 8: a 96^3 "
+                         "bitgrid at k=768)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "refill", "wide"],
                     help="schedule of the render launches (fastnerf_set_schedule)")
     ap.add_argument("--pmc-kernel", default="k_render<0, 8, false>",
@@ -832,7 +843,8 @@ def main():
     if args.no_variants:
         storages = ["f32"]
     t0 = time.perf_counter()
-    p, beta, caches, sparse, occ = build_caches(spec, storages, not args.no_cpu, "cuda")
+    p, beta, caches, sparse, occ = build_caches(spec, storages, not args.no_cpu, "cuda",
+                                                brick=args.brick)
     torch.cuda.synchronize()
     log(f"scene k={spec.k} occupancy {occ:.4f}, caches {storages} built in "
         f"{time.perf_counter() - t0:.1f}s; resident "
@@ -887,7 +899,7 @@ def main():
                          "(28 ellipsoids + 12 shells, seed 1), "
                          f"{args.views}-view orbit r=4 el=0.5 at 800x800, N=192 samples in "
                          "the box, eps=1e-4, nearest position / bilinear direction lookup, "
-                         "8^3 occupancy bricks, FP32 cache; one step = the whole orbit in one "
+                         f"{args.brick}^3 occupancy bricks, FP32 cache; one step = the whole orbit in one "
                          "persistent launch"),
             "views_per_step": args.views, "width": 800, "height": 800, "N": N,
         },
@@ -908,7 +920,7 @@ def main():
         outs_all.update({st: results[st]["outs"] for st in storages if st != "f32"})
         threads = oracle_threads()
         o = oracle_sample(beta, sparse, spec, views, N, eps, args.cpu_pixels, args.cpu_seconds,
-                          outs_all, threads=threads)
+                          outs_all, threads=threads, brick=args.brick)
         host = host_cpu()
         sample = (f"{o['rays']} random pixels ({args.cpu_pixels} per view over the first "
                   f"{o['nviews']} of the {nv} views) of the same workload, FP64")
@@ -927,8 +939,11 @@ def main():
         units = launch_units(o["totals"], views)
         f32 = o["f32"]
         line["parity"] = {"pixels": f32["checked"], "max_abs_err": f32["worst"],
-                          "failing": f32["fails"], "unchecked": f32["unchecked"], "tol": 1e-4,
-                          "reference": "FP64 oracle, FP32 cache"}
+                          "failing": f32["fails"], "bounded": f32["unchecked"],
+                          "bounded_width_max": f32.get("bound_width_max"), "tol": 1e-4,
+                          "reference": "FP64 oracle, FP32 cache; pixels with more than 3 "
+                                       "ambiguous lookups checked against interval bounds of "
+                                       "all their admissible results"}
         for st, acc in o["other"].items():
             m = acc["se"] / max(1, acc["n"])
             psnr_in[st] = dict(max_abs_err=acc["worst"],

@@ -225,7 +225,9 @@ double fastnerf_model_bytes(double alpha, int64_t k, int64_t l, int32_t D, doubl
 
 /* A continuous-batching render server over resident caches. Requests are
  * admitted while their output fits the arena (bytes of device memory the
- * server owns) and fewer than max_inflight are running; every step renders
+ * server owns; arena_bytes = 0 sizes it to a quarter of the device memory
+ * free at creation, after the scenes are resident) and fewer than
+ * max_inflight are running; every step renders
  * the running requests' tiles, an equal share each of a tile budget, in one
  * persistent launch per (storage format, lookup, component class) group,
  * replayed as a HIP graph on that group's own stream. Requests that arrive

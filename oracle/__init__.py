@@ -65,7 +65,7 @@ class _View(ctypes.Structure):
 
 class _Tol(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("gamma_dir", ctypes.c_double),
-                ("tau_band", ctypes.c_double)]
+                ("tau_band", ctypes.c_double), ("max_choice", ctypes.c_int32)]
 
 
 class _Counts(ctypes.Structure):
@@ -87,7 +87,7 @@ def lib():
         dp = P(ctypes.c_double)
         L.orc_render.argtypes = [P(_Scene), P(_View), P(_Tol), ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                 ctypes.c_void_p, P(_Counts)]
+                                 ctypes.c_void_p, ctypes.c_void_p, P(_Counts)]
         L.orc_render.restype = ctypes.c_int
         L.orc_render_mt.argtypes = L.orc_render.argtypes + [ctypes.c_int32]
         L.orc_render_mt.restype = ctypes.c_int
@@ -185,8 +185,10 @@ def _view(K, c2w, H, W, near, far, N, eps):
 
 
 def _tol(tol):
+    """(gamma, gamma_dir, tau_band[, max_choice]) -> the C struct."""
     t = _Tol()
-    t.gamma, t.gamma_dir, t.tau_band = tol
+    t.gamma, t.gamma_dir, t.tau_band = tol[:3]
+    t.max_choice = int(tol[3]) if len(tol) > 3 else 0
     return t
 
 
@@ -194,9 +196,11 @@ def render(scene: Scene, K, c2w, H, W, near, far, N, eps, pix=None, tol=DEFAULT_
            candidates=True, threads=1):
     """Renders pixels (all when ``pix`` is None). Returns a dict with ``rgba``
     [n,4] (primary result), ``cand`` [n,MAXCAND,4] / ``ncand`` [n] (every
-    admissible result), ``flags`` [n] and ``counts`` (dict). ``threads`` > 1
-    splits the pixel list into that many contiguous bands, one thread each
-    (bitwise the same result)."""
+    admissible result), ``env`` [n,2,4] (lower and upper RGBA bounds of every
+    admissible result: the hull of the enumerated ones, or interval bounds for
+    a pixel with too many ambiguous lookups to enumerate), ``flags`` [n] and
+    ``counts`` (dict). ``threads`` > 1 splits the pixel list into that many
+    contiguous bands, one thread each (bitwise the same result)."""
     v = _view(K, c2w, H, W, near, far, N, eps)
     if pix is None:
         n, pp = H * W, None
@@ -207,10 +211,11 @@ def render(scene: Scene, K, c2w, H, W, near, far, N, eps, pix=None, tol=DEFAULT_
     cand = np.zeros((n, MAXCAND, 4), dtype=np.float64) if candidates else None
     ncand = np.zeros(n, dtype=np.int32) if candidates else None
     flags = np.zeros(n, dtype=np.int32)
+    env = np.zeros((n, 2, 4), dtype=np.float64)
     cnt = _Counts()
     t = _tol(tol) if tol is not None else _tol((0.0, 0.0, 0.0))
     args = (ctypes.byref(scene.struct), ctypes.byref(v), ctypes.byref(t), n, _ptr(pp),
-            _ptr(rgba), _ptr(cand), _ptr(ncand), _ptr(flags), ctypes.byref(cnt))
+            _ptr(rgba), _ptr(cand), _ptr(ncand), _ptr(flags), _ptr(env), ctypes.byref(cnt))
     if threads > 1:
         rc = lib().orc_render_mt(*args, int(threads))
     else:
@@ -218,7 +223,7 @@ def render(scene: Scene, K, c2w, H, W, near, far, N, eps, pix=None, tol=DEFAULT_
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     counts = {f: getattr(cnt, f) for f, _ in _Counts._fields_}
-    return dict(rgba=rgba, cand=cand, ncand=ncand, flags=flags, counts=counts)
+    return dict(rgba=rgba, cand=cand, ncand=ncand, flags=flags, env=env, counts=counts)
 
 
 def pixel_ray(K, c2w, H, W, x, y):
@@ -301,13 +306,21 @@ def dequant_cache(fmt: str, sigma, u):
 
 def matches(rgba_gpu, res, tol):
     """Pass protocol: a pixel passes when its result lies within ``tol``
-    (max-abs over RGBA) of at least one admissible oracle result. Returns
-    (per-pixel best error, pass mask)."""
+    (max-abs over RGBA) of at least one admissible oracle result; a pixel with
+    too many ambiguous lookups to enumerate (UNCHECKED) passes when it lies
+    within ``tol`` of the enclosure of all its admissible results. Returns
+    (per-pixel error, pass mask)."""
     g = np.asarray(rgba_gpu, dtype=np.float64).reshape(-1, 4)
     cand, ncand = res["cand"], res["ncand"]
     err = np.abs(cand - g[:, None, :]).max(axis=2)
     mask = np.arange(cand.shape[1])[None, :] < ncand[:, None]
     err = np.where(mask, err, np.inf).min(axis=1)
+    if "env" in res and "flags" in res:
+        unchecked = (res["flags"] & UNCHECKED) != 0
+        if unchecked.any():
+            lo, hi = res["env"][:, 0], res["env"][:, 1]
+            out = np.maximum(np.maximum(lo - g, g - hi), 0.0).max(axis=1)
+            err = np.where(unchecked, out, err)
     return err, err <= tol
 
 

@@ -502,7 +502,7 @@ static int place_samples(const orc_scene *s, const orc_view *v, const orc_tol *t
       int alt[3] = {w->c[i][0], w->c[i][1], w->c[i][2]};
       alt[ax] = alts[ax];
       if (amb > 1 || records_differ(s, w->c[i], alt)) {
-        if (nch < ORC_MAXCHOICE + 1) ch[nch] = (choice_t){i, ax, alts[ax]};
+        if (nch < ORC_MAXCHOICE_LIMIT + 1) ch[nch] = (choice_t){i, ax, alts[ax]};
         nch++;
       }
     }
@@ -559,7 +559,7 @@ static int dir_choices(const orc_scene *s, const orc_tol *tol, double th, double
     int below = (int)nt - 1, above = (int)nt;
     int alt = j == below ? above : below;
     if (alt != j) {
-      if (nch < ORC_MAXCHOICE + 1) ch[nch] = (choice_t){-1, 3, alt};
+      if (nch < ORC_MAXCHOICE_LIMIT + 1) ch[nch] = (choice_t){-1, 3, alt};
       nch++;
     }
   }
@@ -568,17 +568,158 @@ static int dir_choices(const orc_scene *s, const orc_tol *tol, double th, double
     int below = modl((int)np_ - 1, l), above = modl((int)np_, l);
     int alt = m == below ? above : below;
     if (alt != m) {
-      if (nch < ORC_MAXCHOICE + 1) ch[nch] = (choice_t){-1, 4, alt};
+      if (nch < ORC_MAXCHOICE_LIMIT + 1) ch[nch] = (choice_t){-1, 4, alt};
       nch++;
     }
   }
   return nch;
 }
 
+/* Enclosure of every admissible result of a pixel (reading R13) without
+   enumerating them: per sample the interval of density and of each colour
+   channel over its candidate voxels (both sides of every face within gamma)
+   and candidate direction cells; then, from the last sample to the first,
+   V_i = a_i c_i + (1 - a_i) V_{i+1} (V = the background past the stop) and
+   W_i = a_i + (1 - a_i) W_{i+1} (W = 0 past the stop), so RGB = V_0 and
+   A = W_0. V_i is bilinear in (a, c, V_{i+1}) with a, 1 - a >= 0, so its bounds
+   are at c and V_{i+1} at their own bounds and a at an end of its interval.
+   A stop before sample i is possible once the largest optical depth before it
+   exceeds ln(1/eps) - tau_band and certain once the smallest exceeds
+   ln(1/eps) + tau_band; where possible the bounds take in the background. */
+static void enclose(const orc_scene *s, const orc_view *v, const orc_tol *tol,
+                    const ray_work *w, const double d[3], double th, double ph, int j0, int m0,
+                    double delta, double lo[4], double hi[4]) {
+  int D = s->D, k = s->k, n = w->n;
+  double gamma = tol ? tol->gamma : 0.0, band = tol ? tol->tau_band : 0.0;
+  double lim = v->eps > 0.0 ? log(1.0 / v->eps) : INFINITY;
+  /* candidate direction weights */
+  double betas[4][16];
+  int nb = 0;
+  if (s->dir_linear) {
+    lookup_dir_cells(s, d, j0, m0, betas[0]);
+    nb = 1;
+  } else {
+    choice_t chd[ORC_MAXCHOICE_LIMIT + 1];
+    int nd = dir_choices(s, tol, th, ph, j0, m0, chd, 0);
+    int js[2] = {j0, j0}, ms[2] = {m0, m0}, njs = 1, nms = 1;
+    for (int q = 0; q < nd && q < 2; q++) {
+      if (chd[q].axis == 3) js[njs++] = chd[q].alt;
+      else ms[nms++] = chd[q].alt;
+    }
+    for (int a = 0; a < njs; a++)
+      for (int b = 0; b < nms; b++) lookup_dir_cells(s, d, js[a], ms[b], betas[nb++]);
+  }
+  double *slo = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 8);
+  if (!slo) {
+    for (int c = 0; c < 4; c++) {
+      lo[c] = -INFINITY;
+      hi[c] = INFINITY;
+    }
+    return;
+  }
+  double *shi = slo + n, *clo = slo + 2 * n, *chi = slo + 5 * n;
+  for (int i = 0; i < n; i++) {
+    int cand[3][2], nc[3];
+    for (int ax = 0; ax < 3; ax++) {
+      cand[ax][0] = w->c[i][ax];
+      nc[ax] = 1;
+      int alt;
+      if (!s->pos_linear && gamma > 0.0 &&
+          nn_alternative(grid_coord(s, ax, w->p[i][ax]), k, gamma, w->c[i][ax], &alt))
+        cand[ax][nc[ax]++] = alt;
+    }
+    slo[i] = INFINITY;
+    shi[i] = -INFINITY;
+    for (int c = 0; c < 3; c++) {
+      clo[3 * i + c] = INFINITY;
+      chi[3 * i + c] = -INFINITY;
+    }
+    for (int a = 0; a < nc[0]; a++)
+      for (int b = 0; b < nc[1]; b++)
+        for (int e = 0; e < nc[2]; e++) {
+          int cc[3] = {cand[0][a], cand[1][b], cand[2][e]};
+          double sig, uu[48];
+          if (s->pos_linear)
+            lookup_trilinear(s, w->p[i], &sig, uu);
+          else if (cc[0] < 0 || cc[1] < 0 || cc[2] < 0)
+            fetch_voxel(s, -1, -1, -1, &sig, uu);
+          else
+            fetch_voxel(s, cc[0], cc[1], cc[2], &sig, uu);
+          if (sig < slo[i]) slo[i] = sig;
+          if (sig > shi[i]) shi[i] = sig;
+          for (int q = 0; q < nb; q++)
+            for (int c = 0; c < 3; c++) {
+              double acc = 0.0;
+              for (int dd = 0; dd < D; dd++) acc += betas[q][dd] * uu[3 * dd + c];
+              if (acc < clo[3 * i + c]) clo[3 * i + c] = acc;
+              if (acc > chi[3 * i + c]) chi[3 * i + c] = acc;
+            }
+        }
+  }
+  /* optical depth before each sample: smallest and largest */
+  double *tlo = malloc(sizeof(double) * (size_t)(n + 1) * 2);
+  if (!tlo) {
+    free(slo);
+    for (int c = 0; c < 4; c++) {
+      lo[c] = -INFINITY;
+      hi[c] = INFINITY;
+    }
+    return;
+  }
+  double *thi = tlo + n + 1;
+  tlo[0] = thi[0] = 0.0;
+  for (int i = 0; i < n; i++) {
+    double dl = w->var_dl ? w->dl[i] : delta;
+    tlo[i + 1] = tlo[i] + slo[i] * dl;
+    thi[i + 1] = thi[i] + shi[i] * dl;
+  }
+  double Vlo[3], Vhi[3], Wlo = 0.0, Whi = 0.0;
+  for (int c = 0; c < 3; c++) Vlo[c] = Vhi[c] = s->bg[c];
+  for (int i = n - 1; i >= 0; i--) {
+    if (tlo[i] > lim + band) { /* stopped before sample i in every variant */
+      for (int c = 0; c < 3; c++) Vlo[c] = Vhi[c] = s->bg[c];
+      Wlo = Whi = 0.0;
+      continue;
+    }
+    double dl = w->var_dl ? w->dl[i] : delta;
+    double al = -expm1(-slo[i] * dl), ah = -expm1(-shi[i] * dl);
+    for (int c = 0; c < 3; c++) {
+      double l1 = al * clo[3 * i + c] + (1.0 - al) * Vlo[c];
+      double l2 = ah * clo[3 * i + c] + (1.0 - ah) * Vlo[c];
+      double h1 = al * chi[3 * i + c] + (1.0 - al) * Vhi[c];
+      double h2 = ah * chi[3 * i + c] + (1.0 - ah) * Vhi[c];
+      Vlo[c] = l1 < l2 ? l1 : l2;
+      Vhi[c] = h1 > h2 ? h1 : h2;
+    }
+    double wl1 = al + (1.0 - al) * Wlo, wl2 = ah + (1.0 - ah) * Wlo;
+    double wh1 = al + (1.0 - al) * Whi, wh2 = ah + (1.0 - ah) * Whi;
+    Wlo = wl1 < wl2 ? wl1 : wl2;
+    Whi = wh1 > wh2 ? wh1 : wh2;
+    if (thi[i] > lim - band) { /* a stop before sample i is possible */
+      for (int c = 0; c < 3; c++) {
+        if (s->bg[c] < Vlo[c]) Vlo[c] = s->bg[c];
+        if (s->bg[c] > Vhi[c]) Vhi[c] = s->bg[c];
+      }
+      if (0.0 < Wlo) Wlo = 0.0;
+    }
+  }
+  for (int c = 0; c < 3; c++) {
+    lo[c] = Vlo[c];
+    hi[c] = Vhi[c];
+  }
+  lo[3] = Wlo;
+  hi[3] = Whi;
+  free(slo);
+  free(tlo);
+}
+
 static void render_pixel(const orc_scene *s, const orc_view *v, const orc_tol *tol, int x,
                          int y, ray_work *w, double *ts, double rgba[4], cand_list *cl,
-                         int32_t *flag, orc_counts *cnt) {
+                         int32_t *flag, double env[8], orc_counts *cnt) {
   double o[3], d[3], t0, t1;
+  int maxch = !tol || tol->max_choice == 0 ? ORC_MAXCHOICE
+                                            : (tol->max_choice < 0 ? 0 : tol->max_choice);
+  if (maxch > ORC_MAXCHOICE_LIMIT) maxch = ORC_MAXCHOICE_LIMIT;
   cl->n = 0;
   cl->overflow = 0;
   *flag = 0;
@@ -590,12 +731,14 @@ static void render_pixel(const orc_scene *s, const orc_view *v, const orc_tol *t
     for (int c = 0; c < 3; c++) rgba[c] = s->bg[c];
     rgba[3] = 0.0;
     cand_push(cl, (double[3]){0, 0, 0}, 0.0, s->bg);
+    if (env)
+      for (int c = 0; c < 4; c++) env[c] = env[4 + c] = rgba[c];
     return;
   }
   *flag |= ORC_HIT;
   if (cnt) cnt->hit++;
   double delta = 0.0;
-  choice_t ch[ORC_MAXCHOICE + 1];
+  choice_t ch[ORC_MAXCHOICE_LIMIT + 1];
   int nch = 0;
   if (v->N == 0) {
     place_segments(s, o, d, t0, t1, ts, w);
@@ -609,14 +752,14 @@ static void render_pixel(const orc_scene *s, const orc_view *v, const orc_tol *t
   dir_angles(d, &th, &ph);
   nn_dir_cell(s, th, ph, &j0, &m0);
   nch = dir_choices(s, tol, th, ph, j0, m0, ch, nch);
-  if (nch > ORC_MAXCHOICE) {
+  if (nch > maxch) {
     *flag |= ORC_UNCHECKED;
     nch = 0;
   }
   double beta[16];
   for (int var = 0; var < (1 << nch); var++) {
     int j = j0, m = m0;
-    int saved[ORC_MAXCHOICE];
+    int saved[ORC_MAXCHOICE_LIMIT];
     for (int q = 0; q < nch; q++) {
       if (!(var >> q & 1)) continue;
       if (ch[q].smp >= 0) {
@@ -638,11 +781,25 @@ static void render_pixel(const orc_scene *s, const orc_view *v, const orc_tol *t
   }
   if (cl->overflow) *flag |= ORC_UNCHECKED;
   if (nch > 0 || cl->n > 1) *flag |= ORC_AMBIG;
+  if (!env) return;
+  if (*flag & ORC_UNCHECKED) {
+    enclose(s, v, tol, w, d, th, ph, j0, m0, delta, env, env + 4);
+  } else {
+    for (int c = 0; c < 4; c++) {
+      env[c] = INFINITY;
+      env[4 + c] = -INFINITY;
+    }
+    for (int q = 0; q < cl->n; q++)
+      for (int c = 0; c < 4; c++) {
+        if (cl->rgba[q][c] < env[c]) env[c] = cl->rgba[q][c];
+        if (cl->rgba[q][c] > env[4 + c]) env[4 + c] = cl->rgba[q][c];
+      }
+  }
 }
 
 int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_t npix,
                const int64_t *pix, double *rgba, double *cand, int32_t *ncand,
-               int32_t *flags, orc_counts *counts) {
+               int32_t *flags, double *env, orc_counts *counts) {
   if (!s || !v || !rgba || s->k <= 0 || s->D <= 0 || s->D > 16 || s->l <= 0 || v->N < 0 ||
       (v->N == 0 && s->pos_linear) || v->H <= 0 || v->W <= 0 || !s->beta ||
       (!s->sigma && (!s->slot || s->sb <= 0)))
@@ -670,7 +827,8 @@ int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_
     }
     int x = (int)(id % v->W), y = (int)(id / v->W);
     int32_t f;
-    render_pixel(s, v, tol, x, y, &w, ts, rgba + 4 * q, cl, &f, counts);
+    render_pixel(s, v, tol, x, y, &w, ts, rgba + 4 * q, cl, &f, env ? env + 8 * q : NULL,
+                 counts);
     if (flags) flags[q] = f;
     if (counts) {
       counts->ambiguous_pixels += (f & ORC_AMBIG) != 0;
@@ -697,7 +855,7 @@ typedef struct {
   const orc_tol *tol;
   int64_t n;
   int64_t *pix; /* the band's pixel ids */
-  double *rgba, *cand;
+  double *rgba, *cand, *env;
   int32_t *ncand, *flags;
   orc_counts counts;
   int rc;
@@ -706,13 +864,13 @@ typedef struct {
 static void *band_main(void *arg) {
   orc_band *b = arg;
   b->rc = orc_render(b->s, b->v, b->tol, b->n, b->pix, b->rgba, b->cand, b->ncand, b->flags,
-                     &b->counts);
+                     b->env, &b->counts);
   return NULL;
 }
 
 int orc_render_mt(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_t npix,
                   const int64_t *pix, double *rgba, double *cand, int32_t *ncand,
-                  int32_t *flags, orc_counts *counts, int32_t nthreads) {
+                  int32_t *flags, double *env, orc_counts *counts, int32_t nthreads) {
   if (nthreads < 1 || npix < 0 || !v) return -1;
   if ((int64_t)nthreads > npix) nthreads = npix > 0 ? (int32_t)npix : 1;
   orc_band *bands = calloc((size_t)nthreads, sizeof *bands);
@@ -739,6 +897,7 @@ int orc_render_mt(const orc_scene *s, const orc_view *v, const orc_tol *tol, int
     B->cand = cand ? cand + lo * ORC_MAXCAND * 4 : NULL;
     B->ncand = ncand ? ncand + lo : NULL;
     B->flags = flags ? flags + lo : NULL;
+    B->env = env ? env + 8 * lo : NULL;
     if (pthread_create(&th[b], NULL, band_main, B) != 0) {
       rc = -1;
       break;

@@ -23,8 +23,9 @@
 extern "C" {
 #endif
 
-#define ORC_MAXCAND 32   /* candidate results kept per pixel */
-#define ORC_MAXCHOICE 3  /* ambiguous lookups enumerated per pixel */
+#define ORC_MAXCAND 32        /* candidate results kept per pixel */
+#define ORC_MAXCHOICE 3       /* ambiguous lookups enumerated per pixel (default) */
+#define ORC_MAXCHOICE_LIMIT 5 /* the most that orc_tol.max_choice may ask for */
 
 /* Pixel flags. */
 #define ORC_HIT 1        /* the ray's sample interval is non-empty */
@@ -67,6 +68,8 @@ typedef struct {
   double gamma;         /* voxels: samples this close to a cell boundary may take either voxel */
   double gamma_dir;     /* radians: same for nearest direction cells */
   double tau_band;      /* log-transmittance: stop points this close to ln(1/eps) are both admissible */
+  int32_t max_choice;   /* ambiguous lookups enumerated per pixel: 0 = ORC_MAXCHOICE, < 0 =
+                           none, at most ORC_MAXCHOICE_LIMIT */
 } orc_tol;
 
 typedef struct {
@@ -75,17 +78,20 @@ typedef struct {
 
 /* Renders the listed pixels (pix = linear index y*W + x; NULL = all H*W pixels in
    order). rgba receives the primary result, cand/ncand (may be NULL) every
-   admissible result, flags (may be NULL) the ORC_* bits. Returns 0, or -1 on a
-   bad argument. */
+   admissible result, flags (may be NULL) the ORC_* bits, env (may be NULL; 8
+   doubles per pixel: RGBA lower bounds, then upper bounds) an enclosure of
+   every admissible result: the hull of the enumerated ones, or for an
+   ORC_UNCHECKED pixel interval bounds over all its variants. Returns 0, or -1
+   on a bad argument. */
 int orc_render(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_t npix,
                const int64_t *pix, double *rgba, double *cand, int32_t *ncand,
-               int32_t *flags, orc_counts *counts);
+               int32_t *flags, double *env, orc_counts *counts);
 
 /* orc_render split into nthreads contiguous bands of the pixel list, one
    thread each; bitwise the same results, counts summed. */
 int orc_render_mt(const orc_scene *s, const orc_view *v, const orc_tol *tol, int64_t npix,
                   const int64_t *pix, double *rgba, double *cand, int32_t *ncand,
-                  int32_t *flags, orc_counts *counts, int32_t nthreads);
+                  int32_t *flags, double *env, orc_counts *counts, int32_t nthreads);
 
 /* Pieces of the definition, exposed for the pins. */
 void orc_pixel_ray(const orc_view *v, double x, double y, double o[3], double d[3]);

@@ -249,6 +249,14 @@ extern "C" fastnerf_status fastnerf_server_create(const fastnerf_cache *scenes, 
   if (!scenes || nscenes < 1 || !out) return fail(FASTNERF_EINVAL, "no scenes or null out");
   if (max_inflight < 1 || max_inflight > 4096)
     return fail(FASTNERF_EINVAL, "max_inflight = %d outside [1, 4096]", max_inflight);
+  if (arena_bytes == 0) {
+    // admission by the device's free memory: the arena takes a quarter of
+    // what is free now (the scenes are resident already)
+    size_t free_b = 0, total_b = 0;
+    const hipError_t me = hipMemGetInfo(&free_b, &total_b);
+    if (me != hipSuccess) return hip_fail(me, "free device memory");
+    arena_bytes = (uint64_t)(free_b / 4) & ~(uint64_t)255;
+  }
   if (arena_bytes < 256) return fail(FASTNERF_EINVAL, "arena too small");
   for (int i = 0; i < nscenes; ++i)
     if (!scenes[i] || !scenes[i]->finalized)

@@ -680,3 +680,69 @@ def test_voxel_traversal_termination_bound_and_trilinear_rejected():
     sl = oracle.Scene(beta, sig, u, in_box=True, bg=BG, pos_linear=True)
     with pytest.raises(ValueError):
         oracle.render(sl, v.K, v.c2w, 8, 8, 0.0, 100.0, 0, 0.0)
+
+
+# ---------------------------------------------------------------- enclosure of unchecked pixels
+
+def test_enclosure_contains_every_enumerated_variant():
+    """A pixel with more ambiguous lookups than are enumerated is checked
+    against interval bounds of all its admissible results. With a wide
+    ambiguity band (0.02 voxel on a k = 8 grid), a stop band and nearest
+    direction cells, the pixels that five enumerated choices cover exactly
+    become unenumerated with one choice; every result of the full enumeration
+    lies inside their bounds."""
+    sigma, u, beta = _tiny_random(21, k=8, D=2, l=4, density=0.8)
+    sc = oracle.Scene(beta, sigma, u, dir_linear=False, in_box=True, bg=(0.2, 0.6, 0.9))
+    v = synth.orbit_view(2.6, 0.45, 0.3, 14, 12, 0.0, 10.0, f=9.0)
+    full = oracle.render(sc, v.K, v.c2w, 12, 14, 0.0, 10.0, 24, 0.05, tol=(0.02, 0.05, 0.05, 5))
+    part = oracle.render(sc, v.K, v.c2w, 12, 14, 0.0, 10.0, 24, 0.05, tol=(0.02, 0.05, 0.05, 1))
+    enumerated = (full["flags"] & oracle.UNCHECKED) == 0
+    bounded = ((part["flags"] & oracle.UNCHECKED) != 0) & enumerated
+    assert bounded.sum() >= 40
+    lo, hi = part["env"][:, 0], part["env"][:, 1]
+    for q in np.nonzero(bounded)[0]:
+        cands = full["cand"][q, :full["ncand"][q]]
+        assert len(cands) > 2
+        assert np.all(cands >= lo[q] - 1e-12) and np.all(cands <= hi[q] + 1e-12), q
+    # the bounds are those of the variants, not the trivial colour range
+    width = (hi - lo)[bounded].max(axis=1)
+    assert np.median(width) < 0.2
+    # enumerated pixels: the enclosure is the hull of their results
+    for q in np.nonzero(~((part["flags"] & oracle.UNCHECKED) != 0))[0][:20]:
+        c = part["cand"][q, :part["ncand"][q]]
+        assert np.array_equal(part["env"][q, 0], c.min(0)) and \
+            np.array_equal(part["env"][q, 1], c.max(0))
+
+
+def test_enclosure_is_exact_without_variation():
+    """Every candidate voxel and direction cell of a homogeneous box holds the
+    same values, so the interval bounds of a pixel forced out of the
+    enumeration collapse onto the closed form of the homogeneous medium; with
+    termination, a stop point in the band widens them to both stops, one
+    sample's worth of optical depth apart."""
+    D, N, sig = 2, 64, 3.5
+    uval = np.array([[0.3, -0.2, 0.9], [0.5, 0.1, -0.4]], np.float32).astype(np.float64)
+    bval = np.array([0.25, 0.75])
+    c = bval @ uval
+    bg = np.array([0.1, 0.6, 0.35])
+    sc = _const_scene(6, D, 4, sig, uval, bval, in_box=True, bg=tuple(bg), dir_linear=False)
+    # a ray along +x with phi = 0: on the direction cache's seam, an ambiguous cell
+    K, c2w = _one_ray_view((-4.0, 0.31, -0.17), (0.0, 0.31, -0.17), up=(0.0, 0.0, 1.0))
+    r = oracle.render(sc, K, c2w, 1, 1, 0.0, 100.0, N, 0.0, tol=(1e-3, 1e-5, 1e-3, -1))
+    assert r["flags"][0] & oracle.UNCHECKED
+    T = math.exp(-sig * 2.0)
+    expect = np.concatenate([c * (1 - T) + T * bg, [1 - T]])
+    np.testing.assert_allclose(r["env"][0, 0], expect, atol=1e-12)
+    np.testing.assert_allclose(r["env"][0, 1], expect, atol=1e-12)
+    # termination with the stop point inside the band
+    dl = 2.0 / N
+    n = 12                                    # sigma dl n = 2.1875 crosses the limit
+    lim = sig * dl * (n - 0.5) + 0.01          # between samples n - 1 and n
+    eps = math.exp(-lim)
+    r = oracle.render(sc, K, c2w, 1, 1, 0.0, 100.0, N, eps, tol=(1e-3, 1e-5, 0.2, -1))
+    lo, hi = r["env"][0]
+    for m in (n, n + 1):                      # stop after n or n + 1 samples
+        Tm = math.exp(-sig * dl * m)
+        e = np.concatenate([c * (1 - Tm) + Tm * bg, [1 - Tm]])
+        assert np.all(e >= lo - 1e-12) and np.all(e <= hi + 1e-12), m
+    assert (hi - lo).max() < 0.2

@@ -100,3 +100,29 @@ def test_requests_split_across_steps_equal_standalone_renders():
         assert st["steps"] >= 3, st  # the large requests were split
     finally:
         srv.destroy()
+
+
+def test_arena_sized_from_free_device_memory():
+    """arena_bytes = 0: the server's arena is a quarter of the device memory
+    free at creation (admission by free memory); requests render as alone."""
+    import torch
+    import paper_2103_10380_amd as fn
+    caches = _scenes()
+    free_before, _ = torch.cuda.mem_get_info()
+    srv = fn.Server(caches, arena_bytes=0, max_inflight=4)
+    try:
+        free_after, _ = torch.cuda.mem_get_info()
+        taken = free_before - free_after
+        assert abs(taken - free_before / 4) <= (1 << 30), (free_before, taken)
+        views = [synth.orbit_view(3.0 + 0.3 * i, 0.7 * i, 0.2, 96, 80, 0.0, 100.0)
+                 for i in range(3)]
+        tickets = [srv.submit(i % len(caches), v.K, v.c2w, v.H, v.W, v.near, v.far, 64, 1e-4)
+                   for i, v in enumerate(views)]
+        for i, (v, t) in enumerate(zip(views, tickets)):
+            got, _ = srv.result(t, v.H, v.W)
+            alone = fn.render(caches[i % len(caches)], v.K, v.c2w, v.H, v.W, v.near, v.far, 64,
+                              1e-4)
+            torch.cuda.synchronize()
+            assert torch.equal(got, alone)
+    finally:
+        srv.destroy()
