@@ -129,9 +129,11 @@ fastnerf_status fastnerf_cache_readback(fastnerf_cache cache, float *sigma, floa
 /* Occupancy bitgrid (host copy): nbricks^3 bits, brick index (bz*n + by)*n + bx,
  * bit b in word b/32. words must hold ceil(n^3/32) entries. */
 fastnerf_status fastnerf_cache_occupancy(fastnerf_cache cache, uint32_t *words, int32_t *n);
-/* Empty-space distance field (host copy, after finalize): one byte per brick,
- * same brick order as the bitgrid, holding the max-norm (Chebyshev) distance in
- * bricks to the nearest occupied brick: 0 for an occupied brick, capped at 63.
+/* Empty-space distance field (host copy, after finalize): one byte per
+ * distance brick -- the bitgrid's brick, or 8^3 voxels when the bitgrid's is
+ * smaller (and k a multiple of 8) -- in the bitgrid's brick order, holding the
+ * max-norm (Chebyshev) distance in such bricks to the nearest one holding a
+ * set bit: 0 for such a brick, capped at 63.
  * The renderer skips samples with it; output is unchanged by the skipping
  * (Sec. 4: the caches are sparse, empty space is never sampled). dist must hold
  * n^3 bytes; n receives the bricks per axis (0 without a bitgrid). Test hook. */

@@ -249,6 +249,8 @@ DevCache dev_cache(const fastnerf_cache_s *c) {
   d.nbl = c->nbl;
   d.nbo = c->desc.brick > 0 ? c->nbo : 1;
   d.oshift = c->desc.brick > 0 ? c->oshift : 30;
+  d.nbd = c->desc.brick > 0 ? c->nbd : 1;
+  d.dshift = c->desc.brick > 0 ? c->dshift : 30;
   d.rec_shift = c->rec_shift;
   d.nchunk = c->nchunk;
   d.kf = (float)ds.k;
@@ -377,9 +379,16 @@ extern "C" fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc
   if (desc->brick > 0) {
     c->oshift = ilog2((uint64_t)desc->brick);
     c->nbo = desc->k / desc->brick;
+    // the distance field keeps 8^3 bricks under a finer bitgrid (one byte per
+    // brick of a 4^3 or 2^3 grid would no longer stay in the L2 at k = 768)
+    const int db = desc->brick < 8 && desc->k % 8 == 0 ? 8 : desc->brick;
+    c->dshift = ilog2((uint64_t)db);
+    c->nbd = desc->k / db;
   } else {
     c->oshift = 0;
     c->nbo = 0;
+    c->dshift = 0;
+    c->nbd = 0;
   }
   const uint64_t nlb = (uint64_t)c->nbl * c->nbl * c->nbl;
   // a brick-sparse cache allocates its records once the stored bricks are known
@@ -388,7 +397,8 @@ extern "C" fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc
   const uint64_t beta_bytes = (uint64_t)desc->l * desc->l * dp * sizeof(float);
   const uint64_t nbits = (uint64_t)c->nbo * c->nbo * c->nbo;
   const uint64_t occ_bytes = ((nbits + 31) / 32 + 1) * 4;
-  const uint64_t dist_bytes = nbits > 0 ? nbits : 1;
+  const uint64_t ndist = (uint64_t)c->nbd * c->nbd * c->nbd;
+  const uint64_t dist_bytes = ndist > 0 ? ndist : 1;
   const int nch = 1 + 3 * desc->D;
   const uint64_t nwords = occ_bytes / 4;
   const uint64_t sparse_bytes = desc->sparse ? nlb * 4 + nwords * 4 : 0;  // slot, rank
@@ -570,7 +580,7 @@ extern "C" fastnerf_status fastnerf_cache_finalize(fastnerf_cache c, hipStream_t
       e = launch_occupancy((int)c->desc.storage, dc,
                            c->desc.pos_interp == FASTNERF_LINEAR ? 1 : 0, c->occ, s);
     if (e != hipSuccess) return hip_fail(e, "occupancy");
-    const uint64_t nbr = (uint64_t)c->nbo * c->nbo * c->nbo;
+    const uint64_t nbr = (uint64_t)c->nbd * c->nbd * c->nbd;
     uint8_t *tmp = nullptr;
     e = hipMalloc(&tmp, nbr);
     if (e != hipSuccess) return hip_fail(e, "distance scratch");
@@ -649,9 +659,9 @@ extern "C" fastnerf_status fastnerf_cache_skip_distance(fastnerf_cache c, uint8_
                                                         int32_t *n) {
   if (!c || !n) return fail(FASTNERF_EINVAL, "null argument");
   if (!c->finalized) return fail(FASTNERF_EINVAL, "cache not finalized");
-  *n = c->desc.brick > 0 ? c->nbo : 0;
+  *n = c->desc.brick > 0 ? c->nbd : 0;
   if (c->desc.brick == 0 || !dist) return FASTNERF_OK;
-  const uint64_t nbr = (uint64_t)c->nbo * c->nbo * c->nbo;
+  const uint64_t nbr = (uint64_t)c->nbd * c->nbd * c->nbd;
   HIP_TRY(hipMemcpy(dist, c->dist, nbr, hipMemcpyDeviceToHost));
   return FASTNERF_OK;
 }

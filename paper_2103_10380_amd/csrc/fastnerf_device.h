@@ -10,8 +10,10 @@
 // loads.
 // Occupancy: one bit per brick of 2^oshift voxels, set when any voxel of the
 // brick (widened by one voxel for trilinear lookups) has a stored sigma > 0.
-// Distance field: one byte per brick, the Chebyshev distance in bricks to the
-// nearest occupied brick (0 = occupied, capped at kDistCap).
+// Distance field: one byte per distance brick (the occupancy brick, or 8^3
+// voxels when the occupancy brick is smaller), the Chebyshev distance in such
+// bricks to the nearest one holding an occupied brick (0 = it holds one,
+// capped at kDistCap).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -55,6 +57,8 @@ struct DevCache {
   int nbl;               // layout bricks per axis
   int nbo;               // occupancy bricks per axis (1 without a bitgrid)
   int oshift;            // log2 occupancy brick edge (30 without a bitgrid)
+  int nbd;               // distance-field bricks per axis (1 without a bitgrid)
+  int dshift;            // log2 distance-field brick edge (30 without a bitgrid)
   int rec_shift;         // log2 record stride in bytes
   int nchunk;            // 16-byte chunks per record: RecWords<fmt, maxd_class(D)>::nchunk
   float kf;              // k as float
@@ -142,9 +146,24 @@ template <int FMT, int MAXD> struct RecWords {
 
 // ------------------------------------------------------------------ addressing
 
+// Brick-grid index (bz * n + by) * n + bx with 24-bit multiplies (every
+// operand is below 2^12, the products below 2^24): one full-rate v_mad_u32_u24
+// per multiply-add instead of a 64-bit multiply.
+__device__ __forceinline__ uint32_t grid3(uint32_t bx, uint32_t by, uint32_t bz, uint32_t n) {
+  return __umul24(__umul24(bz, n) + by, n) + bx;
+}
+
+// Nearest voxel coordinate along one axis of grid coordinate g (the cell
+// holding it, upper on a face, with FP32 rounding covered by kTie), clamped to
+// the grid: the same value as min(max((int)(g + kTie), 0), k - 1) with a
+// clamp before the conversion (the conversion truncates towards zero).
+__device__ __forceinline__ int voxel_of(float g, float kmax) {
+  return (int)__builtin_amdgcn_fmed3f(g + kTie, 0.0f, kmax);
+}
+
 __device__ inline uint64_t record_offset(const DevCache &c, int x, int y, int z) {
-  uint32_t lb = ((uint32_t)(z >> 3) * (uint32_t)c.nbl + (uint32_t)(y >> 3)) * (uint32_t)c.nbl +
-                (uint32_t)(x >> 3);
+  uint32_t lb = grid3((uint32_t)(x >> 3), (uint32_t)(y >> 3), (uint32_t)(z >> 3),
+                      (uint32_t)c.nbl);
   if (c.slot) lb = (uint32_t)c.slot[lb];  // brick-sparse: stored brick (0 reads as zero)
   uint32_t li = ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
   return (((uint64_t)lb << 9) | li) << c.rec_shift;
@@ -234,6 +253,25 @@ __device__ inline void rec_colour(const uint32_t *w, const float *cw, float &r, 
   r = cr;
   g = cg;
   b = cb;
+}
+
+// ------------------------------------------------------------------ compositing
+
+// e^{-x} through the hardware base-2 exponential (v_exp_f32): relative error
+// a few ulp for the optical depths of a ray (x up to ln(1/eps) plus one
+// sample), where the library expf spends a dozen instructions on range
+// reduction.
+__device__ __forceinline__ float exp_neg(float x) {
+  return __builtin_amdgcn_exp2f(x * -1.44269504088896341f);
+}
+
+// 1 - e^{-x} for x >= 0 (a sample's opacity): below 1/16 a Taylor polynomial
+// (relative error under 2^-40, no cancellation), above it 1 - exp_neg(x)
+// (relative error about 1e-6 there).
+__device__ __forceinline__ float opacity(float x) {
+  const float p = x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f -
+                  x * (1.0f / 120.0f - x * (1.0f / 720.0f))))));
+  return x < 0.0625f ? p : 1.0f - exp_neg(x);
 }
 
 // ------------------------------------------------------------------ direction cache

@@ -24,6 +24,7 @@ struct fastnerf_cache_s {
   unsigned *amax = nullptr;    // FP8 absmax accumulators (float bits)
   int stride = 0, payload = 0, rec_shift = 0, nchunk = 0;
   int nbl = 0, nbo = 0, oshift = 0;
+  int nbd = 0, dshift = 0;      // distance-field bricks per axis, log2 edge (>= the bitgrid's)
   uint64_t resident = 0, occ_bytes = 0;
   bool scales_ready = false, finalized = false;
   hipEvent_t last_use = nullptr;

@@ -180,9 +180,13 @@ __device__ __forceinline__ void ray_window(const DevCache &c, Ray<FMT, MAXD> &r,
   using RW = RecWords<FMT, MAXD>;
   const int k = c.k;
   const float kf = c.kf;
+  const float kmax = (float)(k - 1);
   const int N = r.N;
   const float dt = r.dt;
-  const float bedge = (float)(1 << c.oshift);
+  const float bedge = (float)(1 << c.dshift);
+  // sample i + j sits at distance (i + j + 1/2) dt: fi + (j + 1/2) is exact,
+  // so the scan and the gather below compute the same positions
+  const float fi = (float)r.i;
   uint32_t mask = 0u;
   int next = r.i + kWin;
   uint32_t sslot[SPARSE ? kWin : 1];  // stored brick of each sample (SPARSE)
@@ -193,23 +197,22 @@ __device__ __forceinline__ void ray_window(const DevCache &c, Ray<FMT, MAXD> &r,
     bool in[kWin];
 #pragma unroll
     for (int j = 0; j < kWin; ++j) {
-      const float t = ((float)(r.i + j) + 0.5f) * dt;
+      const float t = (fi + ((float)j + 0.5f)) * dt;
       const float gx = fmaf(t, r.gd[0], r.og[0]), gy = fmaf(t, r.gd[1], r.og[1]),
                   gz = fmaf(t, r.gd[2], r.og[2]);
       // inside the box: 0 <= g <= k on every axis
       in[j] = (r.i + j < N) && fminf(fminf(gx, gy), gz) >= 0.0f &&
               fmaxf(fmaxf(gx, gy), gz) <= kf;
       // clamped voxel: always a valid address, even when not inside
-      const int x = min(max((int)(gx + kTie), 0), k - 1),
-                y = min(max((int)(gy + kTie), 0), k - 1),
-                z = min(max((int)(gz + kTie), 0), k - 1);
-      const uint32_t bit = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo +
-                            (uint32_t)(y >> c.oshift)) * (uint32_t)c.nbo +
-                           (uint32_t)(x >> c.oshift);
+      const int x = voxel_of(gx, kmax), y = voxel_of(gy, kmax), z = voxel_of(gz, kmax);
+      const uint32_t bit = grid3((uint32_t)x >> c.oshift, (uint32_t)y >> c.oshift,
+                                 (uint32_t)z >> c.oshift, (uint32_t)c.nbo);
       word[j] = __ldg(c.occ + (bit >> 5));
       bitpos[j] = bit & 31u;
       if (SPARSE) rk[(SPARSE ? j : 0)] = __ldg(c.rank + (bit >> 5));
-      if (j == kWin - 1) dlast = __ldg(c.dist + bit);
+      if (j == kWin - 1)
+        dlast = __ldg(c.dist + grid3((uint32_t)x >> c.dshift, (uint32_t)y >> c.dshift,
+                                     (uint32_t)z >> c.dshift, (uint32_t)c.nbd));
     }
 #pragma unroll
     for (int j = 0; j < kWin; ++j)
@@ -252,7 +255,7 @@ __device__ __forceinline__ void ray_window(const DevCache &c, Ray<FMT, MAXD> &r,
           for (int q = 1; q < kWin; ++q) v = q == j ? sslot[(SPARSE ? q : 0)] : v;
           sb[b] = v;
         }
-        const float t = ((float)(r.i + j) + 0.5f) * dt;
+        const float t = (fi + ((float)j + 0.5f)) * dt;
         const float gx = fmaf(t, r.gd[0], r.og[0]), gy = fmaf(t, r.gd[1], r.og[1]),
                     gz = fmaf(t, r.gd[2], r.og[2]);
         if (LIN) {
@@ -265,9 +268,9 @@ __device__ __forceinline__ void ray_window(const DevCache &c, Ray<FMT, MAXD> &r,
           wy[b] = hy - fy0;
           wz[b] = hz - fz0;
         } else {
-          vx[b] = min((int)(gx + kTie), k - 1);
-          vy[b] = min((int)(gy + kTie), k - 1);
-          vz[b] = min((int)(gz + kTie), k - 1);
+          vx[b] = voxel_of(gx, kmax);
+          vy[b] = voxel_of(gy, kmax);
+          vz[b] = voxel_of(gz, kmax);
           wx[b] = wy[b] = wz[b] = 0.0f;
         }
       } else {
@@ -304,7 +307,7 @@ __device__ __forceinline__ void ray_window(const DevCache &c, Ray<FMT, MAXD> &r,
         cg = use ? cg : 0.0f;
         cb = use ? cb : 0.0f;
         const float sd = use ? s * dt : 0.0f;
-        const float wgt = expf(-r.tau) * -expm1f(-sd);
+        const float wgt = exp_neg(r.tau) * opacity(sd);
         r.cr = fmaf(wgt, cr, r.cr);
         r.cg = fmaf(wgt, cg, r.cg);
         r.cb = fmaf(wgt, cb, r.cb);
@@ -337,7 +340,7 @@ __device__ __forceinline__ void ray_window(const DevCache &c, Ray<FMT, MAXD> &r,
           cb = fmaf(wt, bq, cb);
         }
         const float sd = s * dt;
-        const float wgt = expf(-r.tau) * -expm1f(-sd);
+        const float wgt = exp_neg(r.tau) * opacity(sd);
         r.cr = fmaf(wgt, cr, r.cr);
         r.cg = fmaf(wgt, cg, r.cg);
         r.cb = fmaf(wgt, cb, r.cb);
@@ -466,7 +469,7 @@ __device__ __forceinline__ void render_tile_vox(const RenderArgs &a, const DevCa
       igd[ax] = step[ax] != 0 ? 1.0f / gd[ax] : 0.0f;
     }
     const float gmax = fmaxf(fabsf(gd[0]), fmaxf(fabsf(gd[1]), fabsf(gd[2])));
-    const float bedge = (float)(1 << c.oshift);
+    const float bedge = (float)(1 << c.dshift);
     // traversal state: position s along [0, L], current cell, next crossings
     float sc = 0.0f;
     int cell[3];
@@ -488,7 +491,7 @@ __device__ __forceinline__ void render_tile_vox(const RenderArgs &a, const DevCa
         restart = false;
       }
       // the window's pieces: record index, bitgrid bit, length
-      uint32_t rec[kVWin], bit[kVWin];
+      uint32_t rec[kVWin], bit[kVWin], dbrick = 0u;
       float len[kVWin];
       uint32_t valid = 0u;
 #pragma unroll
@@ -503,6 +506,9 @@ __device__ __forceinline__ void render_tile_vox(const RenderArgs &a, const DevCa
         rec[j] = (lb << 9) | ((uint32_t)(z & 7) << 6) | ((uint32_t)(y & 7) << 3) | (uint32_t)(x & 7);
         bit[j] = ((uint32_t)(z >> c.oshift) * (uint32_t)c.nbo + (uint32_t)(y >> c.oshift)) *
                      (uint32_t)c.nbo + (uint32_t)(x >> c.oshift);
+        if (j == kVWin - 1)
+          dbrick = grid3((uint32_t)x >> c.dshift, (uint32_t)y >> c.dshift,
+                         (uint32_t)z >> c.dshift, (uint32_t)c.nbd);
         // advance every axis whose boundary is crossed at se
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -516,7 +522,7 @@ __device__ __forceinline__ void render_tile_vox(const RenderArgs &a, const DevCa
       uint32_t word[kVWin];
 #pragma unroll
       for (int j = 0; j < kVWin; ++j) word[j] = __ldg(c.occ + (bit[j] >> 5));
-      const uint32_t dlast = __ldg(c.dist + bit[kVWin - 1]);
+      const uint32_t dlast = __ldg(c.dist + dbrick);
       uint32_t mask = 0u;
 #pragma unroll
       for (int j = 0; j < kVWin; ++j) mask |= ((word[j] >> (bit[j] & 31u)) & 1u) << j;
@@ -803,11 +809,11 @@ __device__ __forceinline__ void render_refill(const RenderArgs &a) {
 }
 
 // Waves per SIMD asked of the compiler for the dense render kernel: FP16/BF16
-// nearest lookups with up to 8 components keep 4 (a few spilled bytes; 9%
-// faster for batched launches than the 3 they would get), the others are
-// left to the compiler.
+// nearest lookups with up to 8 components keep 4 (9% faster for batched
+// launches than the 3 they would get), E4M3 keeps 3; the others are left to
+// the compiler (FP32 fits 4 by itself).
 constexpr int render_waves(int fmt, int maxd, bool lin) {
-  return (fmt == 1 || fmt == 2) && maxd <= 8 && !lin ? 4 : 1;
+  return maxd <= 8 && !lin ? ((fmt == 1 || fmt == 2) ? 4 : (fmt == 3 ? 3 : 1)) : 1;
 }
 
 template <int FMT, int MAXD, bool LIN>
@@ -826,9 +832,9 @@ __global__ void __launch_bounds__(kBlock) k_render_wide(RenderArgs a) {
 
 // The same over the refill schedule (wave-level ray queue), compiled for 4
 // waves per SIMD with nearest lookups in FP32/FP16/BF16 and up to 8 components
-// (as the tile kernel runs).
+// and 3 in E4M3 (as the tile kernel runs).
 constexpr int refill_waves(int fmt, int maxd, bool lin) {
-  return fmt != 3 && maxd <= 8 && !lin ? 4 : 1;
+  return maxd <= 8 && !lin ? (fmt == 3 ? 3 : 4) : 1;
 }
 template <int FMT, int MAXD, bool LIN>
 __global__ void __launch_bounds__(kBlock)
@@ -1049,11 +1055,24 @@ __global__ void k_occupancy(DevCache c, int dilate, uint32_t *__restrict__ words
 }
 
 // Brick distance field, step 1: 0 for occupied bricks, kDistCap otherwise.
-__global__ void k_dist_init(const uint32_t *__restrict__ words, int64_t nbr,
+// Initial distance of each distance brick: 0 when any of the ratio^3 bitgrid
+// bricks it holds is set, kDistCap otherwise (nbo = nbd * ratio).
+__global__ void k_dist_init(const uint32_t *__restrict__ words, int nbd, int nbo, int ratio,
                             uint8_t *__restrict__ out) {
+  const int64_t nbr = (int64_t)nbd * nbd * nbd;
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nbr;
-       b += (int64_t)gridDim.x * blockDim.x)
-    out[b] = ((words[b >> 5] >> (b & 31)) & 1u) ? 0 : kDistCap;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int bx = (int)(b % nbd), by = (int)((b / nbd) % nbd), bz = (int)(b / ((int64_t)nbd * nbd));
+    bool any = false;
+    for (int dz = 0; dz < ratio && !any; ++dz)
+      for (int dy = 0; dy < ratio && !any; ++dy)
+        for (int dx = 0; dx < ratio && !any; ++dx) {
+          const int64_t f = ((int64_t)(bz * ratio + dz) * nbo + (by * ratio + dy)) * nbo +
+                            (bx * ratio + dx);
+          any = (words[f >> 5] >> (f & 31)) & 1u;
+        }
+    out[b] = any ? 0 : kDistCap;
+  }
 }
 
 // One axis of the Chebyshev (max-norm) distance transform, which separates:
@@ -1412,11 +1431,12 @@ hipError_t launch_brick_flags(const float *sigma, int z0, int nz, int k, int nbl
 
 hipError_t launch_distance(const DevCache &c, const uint32_t *words, uint8_t *dist, uint8_t *tmp,
                            hipStream_t s) {
-  const int nb = c.nbo;
+  const int nb = c.nbd;
   const int64_t nbr = (int64_t)nb * nb * nb;
   int64_t blocks = (nbr + kBlock - 1) / kBlock;
   const int grid = (int)(blocks < 65536 ? (blocks < 1 ? 1 : blocks) : 65536);
-  hipLaunchKernelGGL(k_dist_init, dim3(grid), dim3(kBlock), 0, s, words, nbr, tmp);
+  hipLaunchKernelGGL(k_dist_init, dim3(grid), dim3(kBlock), 0, s, words, nb, c.nbo,
+                     1 << (c.dshift - c.oshift), tmp);
   hipLaunchKernelGGL(k_dist_axis, dim3(grid), dim3(kBlock), 0, s, tmp, dist, nb, 0);
   hipLaunchKernelGGL(k_dist_axis, dim3(grid), dim3(kBlock), 0, s, dist, tmp, nb, 1);
   hipLaunchKernelGGL(k_dist_axis, dim3(grid), dim3(kBlock), 0, s, tmp, dist, nb, 2);

@@ -94,17 +94,21 @@ def test_linearity_in_radiance():
 
 
 def test_skip_distance_is_chessboard_distance():
-    """The per-brick skip distance equals scipy's chessboard distance transform
-    of the occupancy bitgrid, capped at 63 (library routine)."""
+    """The skip distance equals scipy's chessboard distance transform of the
+    occupancy, capped at 63 (library routine): over the bitgrid's bricks, or
+    for bitgrids finer than 8^3 over 8^3 bricks holding any set bit."""
     from scipy import ndimage
     sig, u, beta = G.config1_scene()
-    for brick, lin in ((8, False), (4, True), (16, False)):
+    for brick, lin in ((8, False), (4, True), (2, False), (16, False)):
         cache = G.make_cache(sig, u, beta, pos_linear=lin, brick=brick)
         occ = cache.occupancy()
         dist = cache.skip_distance()
         assert occ.any() and not occ.all()
-        ref = np.minimum(ndimage.distance_transform_cdt(~occ, metric="chessboard"), 63)
-        assert np.array_equal(dist, ref)
+        f = max(1, 8 // brick)
+        n = occ.shape[0] // f
+        occ_d = occ.reshape(n, f, n, f, n, f).any(axis=(1, 3, 5))
+        ref = np.minimum(ndimage.distance_transform_cdt(~occ_d, metric="chessboard"), 63)
+        assert np.array_equal(dist, ref), brick
     assert G.make_cache(sig, u, beta, brick=0).skip_distance().size == 0
 
 
