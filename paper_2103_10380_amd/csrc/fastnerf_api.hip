@@ -151,6 +151,11 @@ struct LaunchPlan {
   int block, grid;
 };
 
+// 32-bit words of a cache's occupancy bitgrid (one word without a bitgrid).
+int occ_words_of(const fastnerf_cache_s *c) {
+  return c->desc.brick > 0 ? (int)(((uint64_t)c->nbo * c->nbo * c->nbo + 31) / 32) : 1;
+}
+
 LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox, int sched) {
   static std::mutex mu;
   static std::map<std::pair<int, int>, int> plans;  // (device, variant) -> resident blocks
@@ -159,8 +164,12 @@ LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox, int
   const bool lin = c->desc.pos_interp == FASTNERF_LINEAR;
   const bool sparse = c->desc.sparse && !vox;
   if (vox) sched = kSchedTiles;
+  const int occ_words = occ_words_of(c);
+  const int block = vox ? kBlock
+                        : render_block((int)c->desc.storage, lin, c->desc.D, sparse, sched,
+                                       occ_words);
   const int variant = (int)c->desc.storage * 256 + sched * 64 + (lin ? 32 : 0) +
-                      (vox ? 16 : 0) + (sparse ? 8 : 0) +
+                      (vox ? 16 : 0) + (sparse ? 8 : 0) + (block != kBlock ? 4 : 0) +
                       (c->desc.D <= 4 ? 0 : c->desc.D <= 8 ? 1 : 2);
   int blocks;
   {
@@ -174,13 +183,13 @@ LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox, int
         cus = 1;
       const int per_cu = vox ? render_vox_occupancy((int)c->desc.storage, c->desc.D)
                              : render_occupancy((int)c->desc.storage, lin, c->desc.D, sparse,
-                                                sched);
+                                                sched, occ_words);
       it = plans.emplace(key, cus * (per_cu < 1 ? 1 : per_cu)).first;
     }
     blocks = it->second;
   }
   LaunchPlan p;
-  p.block = kBlock;
+  p.block = block;
   const int wpb = p.block / kWave;
   const int need = (total_tiles + wpb - 1) / wpb;
   p.grid = need < blocks ? (need < 1 ? 1 : need) : blocks;
@@ -248,6 +257,7 @@ DevCache dev_cache(const fastnerf_cache_s *c) {
   d.bq = (ds.D + 3) / 4;
   d.nbl = c->nbl;
   d.nbo = c->desc.brick > 0 ? c->nbo : 1;
+  d.occ_words = occ_words_of(c);
   d.oshift = c->desc.brick > 0 ? c->oshift : 30;
   d.nbd = c->desc.brick > 0 ? c->nbd : 1;
   d.dshift = c->desc.brick > 0 ? c->dshift : 30;
@@ -396,7 +406,9 @@ extern "C" fastnerf_status fastnerf_cache_create_empty(const fastnerf_cache_desc
   const int dp = (desc->D + 3) / 4 * 4;  // direction-cache row, padded to 16 bytes
   const uint64_t beta_bytes = (uint64_t)desc->l * desc->l * dp * sizeof(float);
   const uint64_t nbits = (uint64_t)c->nbo * c->nbo * c->nbo;
-  const uint64_t occ_bytes = ((nbits + 31) / 32 + 1) * 4;
+  // one word more than the bitgrid, rounded up to 16 bytes (the LDS-staged
+  // kernels copy whole 16-byte chunks)
+  const uint64_t occ_bytes = ((nbits + 31) / 32 + 1 + 3) / 4 * 16;
   const uint64_t ndist = (uint64_t)c->nbd * c->nbd * c->nbd;
   const uint64_t dist_bytes = ndist > 0 ? ndist : 1;
   const int nch = 1 + 3 * desc->D;

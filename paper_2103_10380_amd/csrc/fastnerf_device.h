@@ -22,6 +22,10 @@ namespace fnr {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+// Occupancy words the LDS-staged tile kernel can hold: 128 KiB of the CU's
+// 160 KiB, a bitgrid of up to 1,048,576 bricks (k = 768 at 8^3 bricks needs
+// 27,648 words).
+constexpr int kOccLdsWords = 32768;
 constexpr int kMaxD = 16;
 constexpr int kMaxCh = 1 + 3 * kMaxD;
 
@@ -48,6 +52,7 @@ struct DevCache {
   const uint8_t *rec;
   const float *beta;
   const uint32_t *occ;   // occupancy bits (one all-ones word without a bitgrid)
+  int occ_words;         // 32-bit words of occ
   const uint8_t *dist;   // per-brick distance to the nearest occupied brick (one 0 without)
   const float *scales;   // kMaxCh per-channel scales (FP8; ones past 1 + 3D and otherwise)
   const int32_t *slot;   // brick-sparse: record brick of each 8^3 brick (0: all zero); else null

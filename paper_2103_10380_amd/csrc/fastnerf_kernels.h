@@ -6,7 +6,10 @@ namespace fnr {
 
 // Resident blocks per CU of the render kernel (0 if it cannot launch):
 // brick-sparse or dense cache, schedule kSched*.
-int render_occupancy(int fmt, bool lin, int D, bool sparse, int sched);
+int render_occupancy(int fmt, bool lin, int D, bool sparse, int sched, int occ_words);
+// Threads per block of that kernel: kBlock, or one CU's worth for the tile
+// kernel that stages the bitgrid (occ_words 32-bit words) in LDS.
+int render_block(int fmt, bool lin, int D, bool sparse, int sched, int occ_words);
 // Tile queues of a render launch and the spacing of their counters (uints):
 // the counter buffer of a stream holds kQueueCounters uints.
 constexpr int kQueueCounters = 32 * 32;
