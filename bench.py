@@ -706,7 +706,49 @@ def counter_means(root, counter):
     return {name: tot / max(1, len(ids)) for name, (tot, ids) in acc.items()}
 
 
-def pmc_traffic(fetch_dir, write_dir, tcc_dir=None, kernel="k_render<0, 8, false>",
+def line_ceiling(gib=32, regions_kib=(64, 2048, 65536), blocks=16384, iters=32):
+    """Sustained rate of random 128-byte line reads on this GPU (liblinebench.so):
+    each wave reads random lines inside a random region per round, lanes reading
+    whole lines, 32-byte pieces, or one line per 8 lanes. The render's record
+    gathers reach HBM as such lines, so this is the achievable rate they are
+    measured against (the HBM peak assumes streaming)."""
+    import ctypes
+    import torch
+    lb = ctypes.CDLL(os.path.join(ROOT, "paper_2103_10380_amd", "liblinebench.so"))
+    fnl = lb.fnr_line_gather
+    fnl.restype = ctypes.c_int
+    fnl.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                    ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+    nbytes = gib << 30
+    buf = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(4, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    lines = blocks * 256 * iters
+    rates = {}
+    for mode, name in ((0, "line_per_lane"), (1, "32B_per_lane"), (2, "line_per_8_lanes")):
+        for rk in regions_kib:
+            def go(seed):
+                rc = fnl(buf.data_ptr(), nbytes, rk << 10, mode, blocks, iters, seed,
+                         sink.data_ptr(), st.cuda_stream)
+                if rc != 0:
+                    raise RuntimeError(f"fnr_line_gather failed ({rc})")
+            go(1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for r in range(3):
+                go(2 + r)
+            e1.record(st)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            rates[f"{name}_region_{rk}KiB"] = round(lines / ms / 1e6, 2)
+    del buf
+    torch.cuda.empty_cache()
+    best = max(rates.values())
+    return {"unit": "G lines/s", "buffer_gib": gib, "lines_per_launch": lines, "rates": rates,
+            "max_glines_per_s": best, "max_tb_per_s_of_lines": round(best * 128 / 1e3, 3)}
+
+
+def pmc_traffic(fetch_dir, write_dir, tcc_dir=None, kernel="k_render_locc<0, 8, false>",
                 calib="neg_kernel"):
     """HBM bytes per launch of the render kernel from FETCH_SIZE and WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
@@ -776,11 +818,18 @@ def main():
                          "bitgrid at k=768)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "refill", "wide"],
                     help="schedule of the render launches (fastnerf_set_schedule)")
-    ap.add_argument("--pmc-kernel", default="k_render<0, 8, false>",
+    ap.add_argument("--line-ceiling", action="store_true",
+                    help="only measure the random 128-byte line read rate (liblinebench.so)")
+    ap.add_argument("--pmc-kernel", default="k_render_locc<0, 8, false>",
                     help="kernel name (substring) that --pmc-traffic reports")
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile))
+        return
+    if args.line_ceiling:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(line_ceiling()), flush=True)
         return
     if args.step_gaps:
         print(step_gaps(args.step_gaps))
@@ -963,7 +1012,8 @@ def main():
         line["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"k_render<FP32, D<=8, nearest>, {nv} views per launch",
+            "kernel": (f"k_render_locc<FP32, D<=8, nearest> (tile kernel, bitgrid in LDS), "
+                       f"{nv} views per launch"),
             "algorithmic_bytes_per_launch": round(ab["total"]),
             "bytes_per_launch": {key: round(ab[key]) for key in ("records", "beta", "writes")},
             "frac_records_and_writes": round((ab["records"] + ab["writes"]) / avg_s / 1e9 /
@@ -1079,6 +1129,22 @@ def main():
         log(f"precision sweep: {line['precision_sweep']}")
         line["bake"] = bake_measure(fn, with_cpu=not args.no_cpu)
         log(f"bake: {line['bake']}")
+        lc = line_ceiling()
+        line["line_ceiling"] = lc
+        log(f"line ceiling: {lc}")
+        rl = line.get("roofline")
+        if rl is not None:
+            # lines the FP32 launch fetched (L2 misses, from the counters of this
+            # kernel source) per second, against the ceiling just measured
+            miss = None
+            if os.path.exists(PMC_SUMMARY):
+                pmc = json.load(open(PMC_SUMMARY))
+                if pmc.get("kernel_digest") == kernel_digest():
+                    miss = pmc.get("tcc_miss")
+            if miss:
+                rate = miss / (rl["launch_ms_mean"] / 1e3) / 1e9
+                rl["line_rate_glines_per_s"] = round(rate, 2)
+                rl["frac_of_line_ceiling"] = round(rate / lc["max_glines_per_s"], 4)
     line["kernel_digest"] = kernel_digest()
     print(json.dumps(line), flush=True)
 

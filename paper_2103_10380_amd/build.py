@@ -1,4 +1,6 @@
-"""Builds libfastnerf.so (all HIP sources, gfx950) in the package directory."""
+"""Builds libfastnerf.so (the render library: all its HIP sources, gfx950) and
+liblinebench.so (the line-gather measurement kernels used by bench.py) in the
+package directory."""
 from __future__ import annotations
 
 import concurrent.futures
@@ -12,6 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfastnerf.so")
 SOURCES = ["fastnerf_kernels.hip", "fastnerf_api.hip", "fastnerf_serve.hip", "fastnerf_bake.hip",
            "fastnerf_direction.hip"]
+LINEBENCH_SRC = "linebench.hip"
+LINEBENCH_LIB = os.path.join(PKG, "liblinebench.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
@@ -43,6 +47,12 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    lb_obj = os.path.join(objdir, LINEBENCH_SRC.replace(".hip", ".o"))
+    _compile(LINEBENCH_SRC, lb_obj, verbose)
+    tmp = LINEBENCH_LIB + ".tmp"
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, lb_obj],
+                   check=True)
+    os.replace(tmp, LINEBENCH_LIB)
     return LIB
 
 

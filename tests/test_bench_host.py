@@ -63,7 +63,7 @@ def _counters(path, counter, rows):
 
 def test_pmc_traffic_calibration(tmp_path):
     neg = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(x)"
-    ren = "void fnr::k_render<0, 8, false>(fnr::RenderArgs)"
+    ren = "void fnr::k_render_locc<0, 8, false>(fnr::RenderArgs)"
     f, w = str(tmp_path / "fetch"), str(tmp_path / "write")
     # the calibration kernel reads 1 GiB but FETCH_SIZE shows half of it
     # (factor 2); counter rows split over two per-XCD records per dispatch
@@ -84,7 +84,7 @@ def test_pmc_traffic_calibration(tmp_path):
 
 def test_pmc_traffic_l2_hit_rate(tmp_path):
     neg = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(x)"
-    ren = "void fnr::k_render<0, 8, false>(fnr::RenderArgs)"
+    ren = "void fnr::k_render_locc<0, 8, false>(fnr::RenderArgs)"
     f, w, t = str(tmp_path / "fetch"), str(tmp_path / "write"), str(tmp_path / "tcc")
     _counters(f, "FETCH_SIZE", [(1, neg, 524288.0), (3, ren, 1000.0)])
     _counters(w, "WRITE_SIZE", [(1, neg, 1048576.0), (2, ren, 200.0)])
@@ -130,3 +130,20 @@ def test_host_cpu_description():
     assert h["nproc"] >= 1 and 1 <= h["usable_cpus"] <= h["nproc"]
     assert isinstance(h["cpu_model"], str) and h["cpu_model"]
     assert bench.oracle_threads() >= 1
+
+
+def test_linebench_library_exports_and_checks_arguments():
+    """The line-gather measurement library loads and exports its entry point;
+    argument errors are caught before any device call (no GPU needed)."""
+    import ctypes
+    lb = ctypes.CDLL(os.path.join(bench.ROOT, "paper_2103_10380_amd", "liblinebench.so"))
+    f = lb.fnr_line_gather
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+    assert f(None, 1 << 20, 1 << 16, 0, 1, 1, 0, None, None) == -1        # null buffers
+    fake = ctypes.c_void_p(16)
+    assert f(fake, 1 << 20, 100, 0, 1, 1, 0, fake, None) == -1            # region not lines
+    assert f(fake, 1 << 20, 1 << 21, 0, 1, 1, 0, fake, None) == -1        # region > buffer
+    assert f(fake, 1 << 20, 1 << 16, 3, 1, 1, 0, fake, None) == -1        # unknown mode
+    assert f(fake, 1 << 20, 1 << 16, 0, 0, 1, 0, fake, None) == -1        # no blocks
