@@ -658,7 +658,7 @@ def step_gaps(path, match="k_render_step", skip=0.2):
     return "\n".join(lines)
 
 
-def summarize_profile(paths, match=("k_render", "k_bake", "neg_kernel")):
+def summarize_profile(paths, match=("k_render", "k_bake", "neg_kernel", "k_line_gather")):
     """Compact text summary of rocprofv3 CSV output (kernel stats and counter
     collections): per-kernel calls and durations, per-dispatch counter means."""
     import csv
@@ -706,7 +706,7 @@ def counter_means(root, counter):
     return {name: tot / max(1, len(ids)) for name, (tot, ids) in acc.items()}
 
 
-def line_ceiling(gib=32, regions_kib=(64, 2048, 65536), blocks=16384, iters=32):
+def line_ceiling(gib=32, regions_kib=(64, 2048, 65536), blocks=16384, iters=32, modes=(0, 1, 2)):
     """Sustained rate of random 128-byte line reads on this GPU (liblinebench.so):
     each wave reads random lines inside a random region per round, lanes reading
     whole lines, 32-byte pieces, or one line per 8 lanes. The render's record
@@ -726,6 +726,8 @@ def line_ceiling(gib=32, regions_kib=(64, 2048, 65536), blocks=16384, iters=32):
     lines = blocks * 256 * iters
     rates = {}
     for mode, name in ((0, "line_per_lane"), (1, "32B_per_lane"), (2, "line_per_8_lanes")):
+        if mode not in modes:
+            continue
         for rk in regions_kib:
             def go(seed):
                 rc = fnl(buf.data_ptr(), nbytes, rk << 10, mode, blocks, iters, seed,
@@ -820,6 +822,11 @@ def main():
                     help="schedule of the render launches (fastnerf_set_schedule)")
     ap.add_argument("--line-ceiling", action="store_true",
                     help="only measure the random 128-byte line read rate (liblinebench.so)")
+    ap.add_argument("--line-regions", default="64,2048,65536",
+                    help="--line-ceiling: region sizes in KiB, comma-separated")
+    ap.add_argument("--line-modes", default="0,1,2",
+                    help="--line-ceiling: 0 line per lane, 1 32 B per lane, 2 line per 8 lanes")
+    ap.add_argument("--line-gib", type=int, default=32, help="--line-ceiling: buffer size")
     ap.add_argument("--pmc-kernel", default="k_render_locc<0, 8, false>",
                     help="kernel name (substring) that --pmc-traffic reports")
     args = ap.parse_args()
@@ -829,7 +836,9 @@ def main():
     if args.line_ceiling:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps(line_ceiling()), flush=True)
+        print(json.dumps(line_ceiling(
+            gib=args.line_gib, regions_kib=tuple(int(x) for x in args.line_regions.split(",")),
+            modes=tuple(int(x) for x in args.line_modes.split(",")))), flush=True)
         return
     if args.step_gaps:
         print(step_gaps(args.step_gaps))
