@@ -818,7 +818,8 @@ def main():
     ap.add_argument("--brick", type=int, default=8,
                     help="occupancy brick edge of the dense caches (the workload's 8: a 96^3 "
                          "bitgrid at k=768)")
-    ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "refill", "wide"],
+    ap.add_argument("--schedule", default="auto",
+                    choices=["auto", "tiles", "refill", "wide", "split"],
                     help="schedule of the render launches (fastnerf_set_schedule)")
     ap.add_argument("--line-ceiling", action="store_true",
                     help="only measure the random 128-byte line read rate (liblinebench.so)")

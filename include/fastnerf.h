@@ -192,17 +192,22 @@ fastnerf_status fastnerf_render_noalloc(fastnerf_cache cache, const float K[9],
  * miss the box are written at once, the others compacted into the pool).
  * WIDE: tiles with more records in flight per lane at fewer waves per SIMD,
  * which shortens the heaviest rays' dependency chains in launches too small
- * to fill the chip. AUTO (the default): WIDE for launches of at most 20,000
- * tiles (about two 800x800 views), TILES otherwise. Every schedule gives
- * bitwise the same image:
- * each ray is computed by one lane with the same arithmetic. Serving steps
- * and voxel traversal (N = 0) use TILES. Returns EINVAL for an unknown
- * value. */
+ * to fill the chip. SPLIT (single views of dense caches with nearest lookups
+ * and D <= 8; other launches asked for it run WIDE): 4x4 pixel tiles with
+ * four lanes per ray, which share each window's occupancy scan and gather
+ * the window's occupied samples four at a time, one per lane; all four lanes
+ * composite the samples in order. AUTO (the default): for launches of at
+ * most 20,000 8x8 tiles (about two 800x800 views) SPLIT where it applies,
+ * WIDE otherwise; TILES for larger launches. Every schedule gives bitwise the
+ * same image: each sample's arithmetic and the order of the composite are the
+ * same. Serving steps and voxel traversal (N = 0) use TILES. Returns EINVAL
+ * for an unknown value. */
 enum {
   FASTNERF_SCHEDULE_AUTO = 0,
   FASTNERF_SCHEDULE_TILES = 1,
   FASTNERF_SCHEDULE_REFILL = 2,
-  FASTNERF_SCHEDULE_WIDE = 3
+  FASTNERF_SCHEDULE_WIDE = 3,
+  FASTNERF_SCHEDULE_SPLIT = 4
 };
 fastnerf_status fastnerf_set_schedule(int32_t schedule);
 int32_t fastnerf_get_schedule(void);

@@ -288,12 +288,12 @@ def render_batch(cache: Cache, views, N, eps, outs=None, stream=None):
     return outs
 
 
-SCHEDULES = {"auto": 0, "tiles": 1, "refill": 2, "wide": 3}
+SCHEDULES = {"auto": 0, "tiles": 1, "refill": 2, "wide": 3, "split": 4}
 
 
 def set_schedule(name: str):
     """Process-wide schedule of fixed-N render launches: "auto", "tiles",
-    "refill" or "wide" (see fastnerf_set_schedule)."""
+    "refill", "wide" or "split" (see fastnerf_set_schedule)."""
     if name not in SCHEDULES:
         raise ValueError(f"unknown schedule {name!r}")
     check(lib().fastnerf_set_schedule(SCHEDULES[name]))

@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <map>
 #include <atomic>
 #include <mutex>
@@ -156,7 +158,8 @@ int occ_words_of(const fastnerf_cache_s *c) {
   return c->desc.brick > 0 ? (int)(((uint64_t)c->nbo * c->nbo * c->nbo + 31) / 32) : 1;
 }
 
-LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox, int sched) {
+LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox, int sched,
+                       int64_t fill_px) {
   static std::mutex mu;
   static std::map<std::pair<int, int>, int> plans;  // (device, variant) -> resident blocks
   int dev = 0;
@@ -191,7 +194,10 @@ LaunchPlan launch_plan(const fastnerf_cache_s *c, int total_tiles, bool vox, int
   LaunchPlan p;
   p.block = block;
   const int wpb = p.block / kWave;
-  const int need = (total_tiles + wpb - 1) / wpb;
+  int need = (total_tiles + wpb - 1) / wpb;
+  // enough threads that the background pass writes about 64 pixels each
+  const int64_t fill_blocks = (fill_px + 64 * (int64_t)p.block - 1) / (64 * (int64_t)p.block);
+  if (fill_blocks > need) need = (int)std::min<int64_t>(fill_blocks, (int64_t)blocks);
   p.grid = need < blocks ? (need < 1 ? 1 : need) : blocks;
   return p;
 }
@@ -218,11 +224,70 @@ void make_view(const fastnerf_cache_s *c, const float K[9], const float c2w[12],
   v->far_ = far_;
   v->H = H;
   v->W = W;
-  v->tiles_x = (W + 7) / 8;
+  v->cx0 = v->cy0 = 0;
+  v->cx1 = W;
+  v->cy1 = H;
   v->tile_begin = tile_begin;
   v->tile_offset = 0;
   v->scene = 0;
   v->out = out;
+}
+
+// Narrows view v's render rectangle to the pixels whose rays can meet the
+// box: with every box corner in front of the camera, the box projects into
+// the convex hull of its corners' projections, so a pixel whose centre ray
+// meets the box lies in the corners' bounding rectangle (widened by a pixel,
+// its edges rounded out to multiples of 8 and clipped to the image). A ray
+// outside it takes no sample in the box, and its pixel is the background
+// however it is sampled. Left whole when a corner is not in front.
+void cull_view(const fastnerf_cache_s *c, const float K[9], const float c2w[12], DevView *v) {
+  double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+  for (int q = 0; q < 8; ++q) {
+    double X[3], Xc[3];
+    for (int a = 0; a < 3; ++a)
+      X[a] = ((q >> a) & 1) ? (double)c->desc.bbox_max[a] : (double)c->desc.bbox_min[a];
+    // camera coordinates: R^T (X - o), R = the first three columns of c2w
+    for (int col = 0; col < 3; ++col) {
+      double s = 0.0;
+      for (int r = 0; r < 3; ++r) s += (double)c2w[4 * r + col] * (X[r] - (double)c2w[4 * r + 3]);
+      Xc[col] = s;
+    }
+    double u[3];
+    for (int r = 0; r < 3; ++r)
+      u[r] = (double)K[3 * r] * Xc[0] + (double)K[3 * r + 1] * Xc[1] + (double)K[3 * r + 2] * Xc[2];
+    if (!(Xc[2] > 1e-9) || !(u[2] > 1e-9)) return;  // not in front: the whole image
+    for (int a = 0; a < 2; ++a) {
+      const double p = u[a] / u[2];
+      if (!std::isfinite(p)) return;
+      lo[a] = std::min(lo[a], p);
+      hi[a] = std::max(hi[a], p);
+    }
+  }
+  const int lim[2] = {v->W, v->H};
+  int r0[2], r1[2];
+  for (int a = 0; a < 2; ++a) {
+    const double l = std::floor(lo[a]) - 1.0, h = std::ceil(hi[a]) + 1.0;
+    const double lc = std::min(std::max(l, 0.0), (double)lim[a]);
+    const double hc = std::min(std::max(h, 0.0), (double)lim[a]);
+    r0[a] = ((int)lc) & ~7;
+    r1[a] = std::min(lim[a], (((int)hc) + 7) & ~7);
+    if (r1[a] < r0[a]) r1[a] = r0[a];
+  }
+  v->cx0 = r0[0];
+  v->cx1 = r1[0];
+  v->cy0 = r0[1];
+  v->cy1 = r1[1];
+}
+
+// Tiles of edge T (8 or 4) covering view v's render rectangle.
+int view_tiles(const DevView &v, int T) {
+  if (v.cx1 <= v.cx0 || v.cy1 <= v.cy0) return 0;
+  return ((v.cx1 + T - 1) / T - v.cx0 / T) * ((v.cy1 + T - 1) / T - v.cy0 / T);
+}
+
+// Pixels of view v outside its render rectangle.
+int64_t view_outside(const DevView &v) {
+  return (int64_t)v.W * v.H - (int64_t)(v.cx1 - v.cx0) * (v.cy1 - v.cy0);
 }
 
 fastnerf_status check_view(const float *K, const float *c2w, int H, int W, float near_,
@@ -302,29 +367,46 @@ static std::atomic<int> g_schedule{FASTNERF_SCHEDULE_AUTO};
 // the chip with the throughput kernels' waves, and are bound by the dependency
 // chains of their heaviest rays: AUTO gives them the wide kernel.
 constexpr int kWideMaxTiles = 20000;
+#ifndef FNR_AUTO_SPLIT
+#define FNR_AUTO_SPLIT 1
+#endif
+constexpr bool kAutoSplit = FNR_AUTO_SPLIT != 0;
 
-// The schedule of a launch (kSched*): AUTO takes the wide kernel for small
+// Whether a launch can take split rays: a single view (no view array) of a
+// dense cache with nearest lookups and at most 8 components.
+bool split_ok(const fastnerf_cache_s *c, const RenderArgs &a) {
+  return !a.views && !c->desc.sparse && c->desc.pos_interp == FASTNERF_NEAREST &&
+         c->desc.D <= 8;
+}
+
+// The schedule of a launch (kSched*): AUTO takes split rays for a small
+// single-view launch that can take them, the wide kernel for other small
 // launches and tiles otherwise (measured on the paper-scale orbit, the refill
 // schedule was slower: its lanes hold rays of different tiles, so the lanes'
 // occupied samples per window are less alike and the gather rounds of a
-// window, the most over the wave's lanes, grow).
-int launch_schedule(const fastnerf_cache_s *c, bool vox, int total_tiles) {
-  (void)c;
-  if (vox) return kSchedTiles;
+// window, the most over the wave's lanes, grow). SPLIT asked for a launch
+// that cannot take it runs WIDE.
+int launch_schedule(const fastnerf_cache_s *c, const RenderArgs &a, int total_tiles) {
+  if (a.vox) return kSchedTiles;
   switch (g_schedule.load(std::memory_order_relaxed)) {
     case FASTNERF_SCHEDULE_TILES: return kSchedTiles;
     case FASTNERF_SCHEDULE_REFILL: return kSchedRefill;
     case FASTNERF_SCHEDULE_WIDE: return kSchedWide;
+    case FASTNERF_SCHEDULE_SPLIT: return split_ok(c, a) ? kSchedSplit : kSchedWide;
     default: break;
   }
-  return total_tiles <= kWideMaxTiles ? kSchedWide : kSchedTiles;
+  if (total_tiles > kWideMaxTiles) return kSchedTiles;
+  return (kAutoSplit && split_ok(c, a)) ? kSchedSplit : kSchedWide;
 }
 
 fastnerf_status enqueue_render(fastnerf_cache_s *c, const RenderArgs &a0, int total_tiles,
                                unsigned *counter, hipStream_t s) {
   RenderArgs a = a0;
-  a.sched = launch_schedule(c, a.vox != 0, total_tiles);
-  const LaunchPlan p = launch_plan(c, total_tiles, a.vox != 0, a.sched);
+  a.sched = launch_schedule(c, a, total_tiles);
+  // split rays take 4x4-pixel tiles
+  if (a.sched == kSchedSplit) total_tiles = view_tiles(a.v0, 4);
+  if (!a.views) a.fill_px = view_outside(a.v0);
+  const LaunchPlan p = launch_plan(c, total_tiles, a.vox != 0, a.sched, a.fill_px);
   a.counter = counter;
   a.nwaves = (unsigned)p.grid * (p.block / kWave);
   a.total_tiles = total_tiles;
@@ -716,13 +798,13 @@ extern "C" fastnerf_status fastnerf_render(fastnerf_cache c, const float K[9],
   memset(&a, 0, sizeof a);
   a.c = dev_cache(c);
   make_view(c, K, c2w, H, W, near_, far_, out, 0, &a.v0);
+  cull_view(c, K, c2w, &a.v0);
   a.v0.N = N;
   a.v0.lim = eps_limit(eps);
   a.views = nullptr;
   a.nviews = 1;
   a.vox = N == 0;
-  const int tiles = ((W + 7) / 8) * ((H + 7) / 8);
-  return enqueue_render(c, a, tiles, ss->counter, s);
+  return enqueue_render(c, a, view_tiles(a.v0, 8), ss->counter, s);
 }
 
 // ------------------------------------------------------------------ allocation-free render
@@ -774,13 +856,13 @@ extern "C" fastnerf_status fastnerf_render_noalloc(fastnerf_cache c, const float
   memset(&a, 0, sizeof a);
   a.c = dev_cache(c);
   make_view(c, K, c2w, H, W, near_, far_, out, 0, &a.v0);
+  cull_view(c, K, c2w, &a.v0);
   a.v0.N = N;
   a.v0.lim = eps_limit(eps);
   a.views = nullptr;
   a.nviews = 1;
   a.vox = N == 0;
-  const int tiles = ((W + 7) / 8) * ((H + 7) / 8);
-  return enqueue_render(c, a, tiles, ctr, s);
+  return enqueue_render(c, a, view_tiles(a.v0, 8), ctr, s);
 }
 
 extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nviews,
@@ -815,9 +897,10 @@ extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nview
   for (int v = 0; v < nviews; ++v) {
     make_view(c, K + 9 * v, c2w + 12 * v, H[v], W[v], near_[v], far_[v], out[v], tb,
               sl->views_host + v);
+    cull_view(c, K + 9 * v, c2w + 12 * v, sl->views_host + v);
     sl->views_host[v].N = N;
     sl->views_host[v].lim = eps_limit(eps);
-    tb += ((W[v] + 7) / 8) * ((H[v] + 7) / 8);
+    tb += view_tiles(sl->views_host[v], 8);
   }
   HIP_TRY(hipMemcpyAsync(sl->views, sl->views_host, sizeof(DevView) * nviews,
                          hipMemcpyHostToDevice, s));
@@ -828,12 +911,16 @@ extern "C" fastnerf_status fastnerf_render_batch(fastnerf_cache c, int32_t nview
   a.views = sl->views;
   a.nviews = nviews;
   a.vox = N == 0;
-  return enqueue_render(c, a, (int)total, ss->counter, s);
+  a.fill_px = 0;
+  for (int v = 0; v < nviews; ++v) a.fill_px += view_outside(sl->views_host[v]);
+  (void)total;
+  return enqueue_render(c, a, tb, ss->counter, s);
 }
 
 extern "C" fastnerf_status fastnerf_set_schedule(int32_t schedule) {
   if (schedule != FASTNERF_SCHEDULE_AUTO && schedule != FASTNERF_SCHEDULE_TILES &&
-      schedule != FASTNERF_SCHEDULE_REFILL && schedule != FASTNERF_SCHEDULE_WIDE)
+      schedule != FASTNERF_SCHEDULE_REFILL && schedule != FASTNERF_SCHEDULE_WIDE &&
+      schedule != FASTNERF_SCHEDULE_SPLIT)
     return fail(FASTNERF_EINVAL, "unknown schedule %d", schedule);
   fnr::g_schedule.store(schedule, std::memory_order_relaxed);
   return FASTNERF_OK;

@@ -78,7 +78,11 @@ struct DevView {
   double M[9];       // R K^-1: pixel (x+1/2, y+1/2, 1) -> world direction
   double o[3];       // camera centre
   float near_, far_;
-  int H, W, tiles_x, tile_begin;
+  int H, W, tile_begin;
+  // pixel rectangle [cx0, cx1) x [cy0, cy1) covered by the view's tiles (edges
+  // multiples of 8 or the image's edge): the pixels outside it cannot see the
+  // box, and the kernel writes them with the background
+  int cx0, cy0, cx1, cy1;
   int tile_offset;   // first tile of the view covered (serving steps cover tile ranges)
   int scene;         // index into RenderArgs::caches (serving)
   int N;             // samples per ray
@@ -97,13 +101,14 @@ struct RenderArgs {
   const DevCache *caches;   // serving: per-scene caches (device), views[i].scene indexes it
   const int *dyn_total;     // serving: {tile count, view count} of the step (device)
   int vox;                  // 1: voxel traversal (every view has N = 0)
+  long long fill_px;        // pixels outside the views' render rectangles (host: grid size)
   int sched;                // kSchedTiles, kSchedRefill or kSchedWide
 };
 
 // Schedules of a fixed-N render launch: one 8x8 tile per wave (tiles), the
 // wave-level ray queue (refill), tiles with more records in flight per lane
 // (wide, for launches with few tiles).
-constexpr int kSchedTiles = 0, kSchedRefill = 1, kSchedWide = 2;
+constexpr int kSchedTiles = 0, kSchedRefill = 1, kSchedWide = 2, kSchedSplit = 3;
 
 // ------------------------------------------------------------------ storage formats
 

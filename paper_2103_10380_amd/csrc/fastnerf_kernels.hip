@@ -180,15 +180,50 @@ __device__ __forceinline__ int skip_from(uint32_t d, int i, float bedge, float i
 constexpr int kSetupJumps = FNR_SETUP_JUMPS;
 
 // The pixel: RGB = C + T bg, A = 1 - T (T = exp(-tau)).
+__device__ __forceinline__ float4 pixel_value(const DevCache &c, float tau, float cr, float cg,
+                                              float cb) {
+  const float T = expf(-tau);
+  float4 res;
+  res.x = fmaf(T, c.bg[0], cr);
+  res.y = fmaf(T, c.bg[1], cg);
+  res.z = fmaf(T, c.bg[2], cb);
+  res.w = -expm1f(-tau);
+  return res;
+}
 template <int FMT, int MAXD>
 __device__ __forceinline__ void ray_finish(const DevCache &c, const Ray<FMT, MAXD> &r) {
-  const float T = expf(-r.tau);
-  float4 res;
-  res.x = fmaf(T, c.bg[0], r.cr);
-  res.y = fmaf(T, c.bg[1], r.cg);
-  res.z = fmaf(T, c.bg[2], r.cb);
-  res.w = -expm1f(-r.tau);
-  *r.out = res;
+  *r.out = pixel_value(c, r.tau, r.cr, r.cg, r.cb);
+}
+
+// Pixel of lane (lx, ly) in tile lt (edge T) of view V's render rectangle.
+template <int T>
+__device__ __forceinline__ void tile_pixel(const DevView &V, int lt, int lx, int ly, int &px,
+                                           int &py) {
+  const int ntx = (V.cx1 + T - 1) / T - V.cx0 / T;
+  px = (V.cx0 / T + lt % ntx) * T + lx;
+  py = (V.cy0 / T + lt / ntx) * T + ly;
+}
+
+// The pixels of the launch's views outside their render rectangles: rays that
+// cannot meet the box, whose pixel is the background (the value a ray with no
+// composited sample gets). All threads of the grid share the work before
+// they take tiles.
+__device__ __forceinline__ void fill_outside(const RenderArgs &a) {
+  const float4 bgp = pixel_value(a.c, 0.0f, 0.0f, 0.0f, 0.0f);
+  const int nv = a.views ? a.nviews : 1;
+  const long long nt = (long long)gridDim.x * blockDim.x;
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int vi = 0; vi < nv; ++vi) {
+    const DevView *V = a.views ? a.views + vi : &a.v0;
+    const int W = V->W, H = V->H, x0 = V->cx0, y0 = V->cy0, x1 = V->cx1, y1 = V->cy1;
+    if (x0 == 0 && y0 == 0 && x1 >= W && y1 >= H) continue;
+    float4 *out = reinterpret_cast<float4 *>(V->out);
+    const long long n = (long long)W * H;
+    for (long long p = gt; p < n; p += nt) {
+      const int y = (int)(p / W), x = (int)(p - (long long)y * W);
+      if (x < x0 || x >= x1 || y < y0 || y >= y1) out[p] = bgp;
+    }
+  }
 }
 
 // One window of kWin samples of a live ray: the occupancy bits of the window
@@ -398,8 +433,8 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const DevCache 
                                             const DevView &V, int lt, int lane,
                                             const uint32_t *locc = nullptr) {
   (void)a;
-  const int px = (lt % V.tiles_x) * 8 + (lane & 7);
-  const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
+  int px, py;
+  tile_pixel<8>(V, lt, lane & 7, lane >> 3, px, py);
   if (px >= V.W || py >= V.H) return;
   Ray<FMT, MAXD> r;
   float beta[MAXD];
@@ -458,8 +493,8 @@ __device__ __forceinline__ void render_tile_vox(const RenderArgs &a, const DevCa
   using RW = RecWords<FMT, MAXD>;
   constexpr int B = Batch<FMT, false>::value;
   const int W = V.W, H = V.H;
-  const int px = (lt % V.tiles_x) * 8 + (lane & 7);
-  const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
+  int px, py;
+  tile_pixel<8>(V, lt, lane & 7, lane >> 3, px, py);
   if (px >= W || py >= H) return;
   const int k = c.k;
   // FP64 ray set-up, as in render_tile; the interval is always clipped to the box
@@ -714,6 +749,7 @@ template <int FMT, int MAXD, bool LIN, bool SPARSE, int B = Batch<FMT, LIN>::val
 __device__ __forceinline__ void render_queue(const RenderArgs &a,
                                              const uint32_t *locc = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
+  fill_outside(a);
   const Queue Q = make_queue(a, a.total_tiles);
   for (;;) {
     const int tile = queue_fetch(Q, lane);
@@ -725,6 +761,192 @@ __device__ __forceinline__ void render_queue(const RenderArgs &a,
     } else {
       render_tile<FMT, MAXD, LIN, SPARSE, B, OL>(a, a.c, a.v0, tile, lane, locc);
     }
+  }
+  queue_retire(Q, lane);
+}
+
+// ------------------------------------------------------------------ split rays
+
+#ifndef FNR_SPLIT_JUMPS
+#define FNR_SPLIT_JUMPS FNR_SETUP_JUMPS
+#endif
+constexpr int kSplitJumps = FNR_SPLIT_JUMPS;
+#ifndef FNR_SPLIT_WAVES
+#define FNR_SPLIT_WAVES 0
+#endif
+
+// Quad (four-lane group) exchanges through DPP: the value of lane Q of each
+// quad to every lane of the quad, and the OR over a quad. Every lane of a
+// quad holds the same ray and takes the same branches around these calls.
+template <int Q>
+__device__ __forceinline__ uint32_t quad_from(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, Q * 0x55, 0xF, 0xF, true);
+}
+template <int Q>
+__device__ __forceinline__ float quad_from(float v) {
+  return __uint_as_float(quad_from<Q>(__float_as_uint(v)));
+}
+__device__ __forceinline__ uint32_t quad_or(uint32_t v) {
+  v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // lanes 1 0 3 2
+  v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // lanes 2 3 0 1
+  return v;
+}
+
+// One window of a ray held by a quad (lane sub = 0..3 of the quad): the scan
+// of the window's kWin samples is shared (lane sub tests samples sub, sub + 4,
+// ...; the quad ORs the bits; lane 3 reads the last sample's brick distance),
+// and each gather round fetches the window's next four occupied samples, one
+// per lane, one record each. Every lane then composites the round's samples
+// in order with the same operations as ray_window, so the ray state stays the
+// same in all four lanes and the image equals the tile schedule's bitwise.
+template <int FMT, int MAXD>
+__device__ __forceinline__ void split_window(const DevCache &c, Ray<FMT, MAXD> &r, bool &alive,
+                                             float s0, int sub) {
+  using RW = RecWords<FMT, MAXD>;
+  const float kf = c.kf;
+  const float kmax = (float)(c.k - 1);
+  const int N = r.N;
+  const float dt = r.dt;
+  const float bedge = (float)(1 << c.dshift);
+  const float fi = (float)r.i;
+  uint32_t part = 0u, dl = 0u;
+  if (alive) {
+    uint32_t word[kWin / 4], bitpos[kWin / 4];
+    bool in[kWin / 4];
+#pragma unroll
+    for (int q = 0; q < kWin / 4; ++q) {
+      const int j = sub + 4 * q;
+      const float t = (fi + ((float)j + 0.5f)) * dt;
+      const float gx = fmaf(t, r.gd[0], r.og[0]), gy = fmaf(t, r.gd[1], r.og[1]),
+                  gz = fmaf(t, r.gd[2], r.og[2]);
+      in[q] = (r.i + j < N) && fminf(fminf(gx, gy), gz) >= 0.0f &&
+              fmaxf(fmaxf(gx, gy), gz) <= kf;
+      const int x = voxel_of(gx, kmax), y = voxel_of(gy, kmax), z = voxel_of(gz, kmax);
+      const uint32_t bit = grid3((uint32_t)x >> c.oshift, (uint32_t)y >> c.oshift,
+                                 (uint32_t)z >> c.oshift, (uint32_t)c.nbo);
+      word[q] = __ldg(c.occ + (bit >> 5));
+      bitpos[q] = bit & 31u;
+      if (q == kWin / 4 - 1 && sub == 3)
+        dl = __ldg(c.dist + grid3((uint32_t)x >> c.dshift, (uint32_t)y >> c.dshift,
+                                  (uint32_t)z >> c.dshift, (uint32_t)c.nbd));
+    }
+#pragma unroll
+    for (int q = 0; q < kWin / 4; ++q)
+      part |= (uint32_t)(in[q] && ((word[q] >> bitpos[q]) & 1u)) << (sub + 4 * q);
+  }
+  uint32_t mask = quad_or(part);
+  const uint32_t dlast = quad_from<3>(dl);
+  int next = r.i + kWin;
+  if (dlast >= 2u) {
+    const float run = fminf(((float)(dlast - 1u) * bedge - 0.5f) * r.inv_step, (float)N);
+    next += (int)run;
+  }
+  uint32_t w[RW::nwords];
+#pragma unroll
+  for (int q = 0; q < RW::nwords; ++q) w[q] = 0u;
+  while (mask != 0u && alive) {
+    // this lane's sample: the (sub + 1)-th lowest set bit of the mask
+    uint32_t m = mask;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (q < sub) m &= m - 1u;
+    const bool have = m != 0u;
+    const int j = have ? __builtin_ctz(m) : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) mask &= mask - 1u;
+    float sd = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+    if (have) {
+#pragma clang fp contract(off)
+      const float t = (fi + ((float)j + 0.5f)) * dt;
+      const float gx = fmaf(t, r.gd[0], r.og[0]), gy = fmaf(t, r.gd[1], r.og[1]),
+                  gz = fmaf(t, r.gd[2], r.og[2]);
+      load_record<FMT, MAXD>(c, record_offset(c, voxel_of(gx, kmax), voxel_of(gy, kmax),
+                                              voxel_of(gz, kmax)),
+                             w);
+      const float sg = rec_sigma<FMT>(w, s0);
+      rec_colour<FMT, MAXD>(w, r.cw, cr, cg, cb);
+      sd = sg * dt;
+    }
+    const uint32_t hv = have ? 1u : 0u;
+    const uint32_t h[4] = {quad_from<0>(hv), quad_from<1>(hv), quad_from<2>(hv),
+                           quad_from<3>(hv)};
+    const float sdq[4] = {quad_from<0>(sd), quad_from<1>(sd), quad_from<2>(sd),
+                          quad_from<3>(sd)};
+    const float crq[4] = {quad_from<0>(cr), quad_from<1>(cr), quad_from<2>(cr),
+                          quad_from<3>(cr)};
+    const float cgq[4] = {quad_from<0>(cg), quad_from<1>(cg), quad_from<2>(cg),
+                          quad_from<3>(cg)};
+    const float cbq[4] = {quad_from<0>(cb), quad_from<1>(cb), quad_from<2>(cb),
+                          quad_from<3>(cb)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma clang fp contract(off)
+      const bool use = h[q] != 0u && alive;
+      const float sdu = use ? sdq[q] : 0.0f;
+      const float wgt = exp_neg(r.tau) * opacity(sdu);
+      r.cr = fmaf(wgt, use ? crq[q] : 0.0f, r.cr);
+      r.cg = fmaf(wgt, use ? cgq[q] : 0.0f, r.cg);
+      r.cb = fmaf(wgt, use ? cbq[q] : 0.0f, r.cb);
+      r.tau = r.tau + sdu;
+      alive = alive && !(r.tau > r.lim);
+    }
+  }
+  if (alive) {
+    r.i = next;
+    if (r.i >= N) alive = false;
+  }
+}
+
+// Renders the 16 rays of one 4x4 tile of a single view, four lanes per ray
+// (lane l: ray l / 4, quarter l % 4): set-up (the same in the four lanes),
+// the set-up jumps, split windows until the ray stops, the pixel (lane 0 of
+// the quad). Dense caches with nearest lookups.
+template <int FMT, int MAXD>
+__device__ __forceinline__ void render_tile_split(const DevCache &c, const DevView &V, int lt,
+                                                  int lane) {
+  const int ray = lane >> 2, sub = lane & 3;
+  int px, py;
+  tile_pixel<4>(V, lt, ray & 3, ray >> 2, px, py);
+  if (px >= V.W || py >= V.H) return;  // the whole quad
+  Ray<FMT, MAXD> r;
+  float beta[MAXD];
+  bool alive = ray_setup<FMT, MAXD>(c, V, px, py, r, beta);
+  if (alive) {
+    uint32_t d = kSplitJumps > 0 ? sample_distance<FMT, MAXD>(c, r, 0) : 0u;
+    ray_weights<FMT, MAXD>(c, beta, r);
+    const float bedge = (float)(1 << c.dshift);
+#pragma unroll
+    for (int q = 0; q < kSplitJumps; ++q) {
+      const int nx = skip_from(d, r.i, bedge, r.inv_step, r.N);
+      d = 0u;
+      if (nx != r.i) {
+        r.i = nx;
+        if (q + 1 < kSplitJumps && nx < r.N) d = sample_distance<FMT, MAXD>(c, r, nx);
+      }
+    }
+    alive = r.i < r.N;
+  }
+  const float s0 = FMT == 3 ? c.scales[0] : 1.0f;
+  while (alive) split_window<FMT, MAXD>(c, r, alive, s0, sub);
+  if (sub == 0) ray_finish<FMT, MAXD>(c, r);
+}
+
+// Single views with split rays: each wave takes 4x4 tiles from its queue.
+// E4M3 is compiled for 4 waves per SIMD (single views 4% faster than at the
+// 3 its registers would give); the others are left to the compiler.
+constexpr int split_waves(int fmt) {
+  return FNR_SPLIT_WAVES > 0 ? FNR_SPLIT_WAVES : (fmt == 3 ? 4 : 1);
+}
+template <int FMT, int MAXD>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(split_waves(FMT)))) k_render_split(RenderArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  fill_outside(a);
+  const Queue Q = make_queue(a, a.total_tiles);
+  for (;;) {
+    const int tile = queue_fetch(Q, lane);
+    if (tile < 0) break;
+    render_tile_split<FMT, MAXD>(a.c, a.v0, tile, lane);
   }
   queue_retire(Q, lane);
 }
@@ -798,6 +1020,7 @@ __device__ __forceinline__ void render_refill(const RenderArgs &a) {
   const int lane = threadIdx.x & (kWave - 1);
   uint32_t(*P)[kWave] = pool[threadIdx.x / kWave];
   const DevCache &c = a.c;
+  fill_outside(a);
   const Queue Q = make_queue(a, a.total_tiles);
   const float s0 = FMT == 3 ? c.scales[0] : 1.0f;
   const uint64_t below = (1ull << lane) - 1ull;  // the lanes before this one
@@ -820,8 +1043,8 @@ __device__ __forceinline__ void render_refill(const RenderArgs &a) {
           }
           const DevView V = a.views ? a.views[view_of_tile(a, tile, a.nviews)] : a.v0;
           const int lt = a.views ? tile - V.tile_begin + V.tile_offset : tile;
-          const int px = (lt % V.tiles_x) * 8 + (lane & 7);
-          const int py = (lt / V.tiles_x) * 8 + (lane >> 3);
+          int px, py;
+          tile_pixel<8>(V, lt, lane & 7, lane >> 3, px, py);
           bool march = false;
           Ray<FMT, MAXD> nr;
           float beta[MAXD];
@@ -964,6 +1187,7 @@ constexpr int sparse_waves(int fmt, int maxd) { return maxd == 16 ? 2 : (fmt == 
 template <int FMT, int MAXD>
 __global__ void __launch_bounds__(kBlock) k_render_vox(RenderArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
+  fill_outside(a);
   const Queue Q = make_queue(a, a.total_tiles);
   for (;;) {
     const int tile = queue_fetch(Q, lane);
@@ -1287,6 +1511,9 @@ const void *render_kernel(int sched, bool sparse, bool locc = false) {
       if (sched == kSchedWide) return (const void *)k_render_sparse_wide<FMT, MAXD>;
       return (const void *)k_render_sparse<FMT, MAXD, sparse_waves(FMT, MAXD)>;
     }
+  }
+  if constexpr (!LIN && MAXD <= 8) {
+    if (sched == kSchedSplit && !sparse) return (const void *)k_render_split<FMT, MAXD>;
   }
   if (sched == kSchedRefill) return (const void *)k_render_refill<FMT, MAXD, LIN>;
   if (sched == kSchedWide) return (const void *)k_render_wide<FMT, MAXD, LIN>;

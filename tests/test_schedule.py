@@ -7,6 +7,7 @@ views and batches of uneven views."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from tests import gpu_util as G
 
@@ -22,17 +23,21 @@ def _restore_schedule():
 
 def _both(fn_render):
     """The render under the tile schedule and under the refill schedule; the
-    wide kernel's render is checked against the tile one here too."""
+    wide kernel's and the split rays' renders (split applies to single views
+    of dense caches with nearest lookups; other launches asked for it run
+    wide) are checked against the tile one here too."""
     import torch
     import paper_2103_10380_amd as fn
     out = {}
-    for sch in ("tiles", "refill", "wide"):
+    for sch in ("tiles", "refill", "wide", "split"):
         fn.set_schedule(sch)
         out[sch] = fn_render()
         torch.cuda.synchronize()
-    a, w = out["tiles"], out["wide"]
-    for x, y in (zip(a, w) if isinstance(a, list) else [(a, w)]):
-        assert torch.equal(x, y)
+    a = out["tiles"]
+    for other in ("wide", "split"):
+        w = out[other]
+        for x, y in (zip(a, w) if isinstance(a, list) else [(a, w)]):
+            assert torch.equal(x, y), other
     return a, out["refill"]
 
 
@@ -94,10 +99,103 @@ def test_refill_paper_like_scene_and_no_grid():
         c.destroy()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "fp8"])
+def test_split_single_views_of_any_size(storage):
+    """Split rays (4x4 tiles, four lanes per ray) on single views whose sides
+    are not multiples of 4 (partial tiles at the right and bottom edges), in
+    the box and between near and far: bitwise the tile schedule's image, and
+    the oracle's within the kernel parity tolerance."""
+    import torch
+    import paper_2103_10380_amd as fn
+    sig, u, beta = G.config1_scene()
+    for in_box in (False, True):
+        cache = G.make_cache(sig, u, beta, storage=storage, in_box=in_box)
+        sc = G.oracle_scene(sig, u, beta, storage=storage, in_box=in_box)
+        for (W, H) in [(37, 29), (1, 3), (8, 8), (13, 66)]:
+            v = synth.orbit_view(3.2, 0.9, 0.3, W, H, 0.0 if in_box else 2.0,
+                                 100.0 if in_box else 4.5)
+            out = {}
+            for sch in ("tiles", "split"):
+                fn.set_schedule(sch)
+                out[sch] = fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, 96, 1e-3)
+                torch.cuda.synchronize()
+            assert torch.equal(out["tiles"], out["split"]), (storage, in_box, H, W)
+            res = G.oracle_render(sc, v, 96, 1e-3)
+            err, failing, _ = G.compare(out["split"].cpu().numpy().reshape(-1, 4)
+                                        .astype(np.float64), res, G.PARITY_TOL)
+            assert failing == 0, (storage, in_box, H, W, err)
+        cache.destroy()
+
+
+def _rect_views():
+    """Views that exercise the render rectangle (the pixels whose rays can meet
+    the box): far (a small rectangle), near (the box overfills the image), the
+    camera inside the box (no rectangle), the box half off the image and wholly
+    off it (principal point moved), a corner behind the camera."""
+    import dataclasses
+    vs = [synth.orbit_view(7.0, 0.3, 0.2, 120, 96, 2.0, 12.0),
+          synth.orbit_view(1.9, 1.1, 0.5, 96, 120, 0.0, 100.0),
+          synth.orbit_view(0.4, 2.0, 0.3, 64, 64, 0.0, 100.0)]
+    base = synth.orbit_view(3.0, 0.7, 0.4, 100, 80, 0.0, 100.0)
+    for shift in (50.0, 400.0):
+        K = base.K.copy()
+        K[0, 2] += shift
+        vs.append(dataclasses.replace(base, K=K))
+    c2w = synth.look_at(synth.orbit_eye(1.3, 0.2, 0.1), target=(5.0, 3.0, 0.0))
+    vs.append(synth.View(synth.intrinsics(72, 56), c2w, 56, 72, 0.0, 100.0))
+    return vs
+
+
+@pytest.mark.parametrize("in_box", [False, True])
+def test_render_rectangle_cases(in_box):
+    """Pixels outside a view's render rectangle are written as background by
+    the kernel's fill pass, the others by the tiles; single views (every
+    schedule), a batch of them and the voxel traversal all match the oracle,
+    and the batch equals the single renders bitwise."""
+    import torch
+    import paper_2103_10380_amd as fn
+    sig, u, beta = G.config1_scene()
+    cache = G.make_cache(sig, u, beta, in_box=in_box)
+    sc = G.oracle_scene(sig, u, beta, in_box=in_box)
+    views = _rect_views()
+    for v in views:
+        if not in_box:
+            v.near, v.far = max(v.near, 0.05), min(v.far, 12.0)
+    singles = []
+    for v in views:
+        res = G.oracle_render(sc, v, 64, 1e-3)
+        outs = {}
+        for sch in ("tiles", "wide", "split", "refill"):
+            fn.set_schedule(sch)
+            outs[sch] = fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, 64, 1e-3)
+            torch.cuda.synchronize()
+        for sch, o in outs.items():
+            assert torch.equal(o, outs["tiles"]), (sch, v.W, v.H)
+        err, failing, _ = G.compare(outs["tiles"].cpu().numpy().reshape(-1, 4)
+                                    .astype(np.float64), res, G.PARITY_TOL)
+        assert failing == 0, (v.W, v.H, err)
+        singles.append(outs["tiles"])
+    fn.set_schedule("auto")
+    batch = fn.render_batch(cache, views, 64, 1e-3)
+    torch.cuda.synchronize()
+    for x, y in zip(batch, singles):
+        assert torch.equal(x, y)
+    # N = 0 (voxel traversal) takes the same rectangles
+    for v in views[:2]:
+        res = oracle.render(sc, v.K, v.c2w, v.H, v.W, v.near, v.far, 0, 1e-3,
+                            tol=oracle.DEFAULT_TOL)
+        out = fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, 0, 1e-3)
+        torch.cuda.synchronize()
+        err, failing, _ = G.compare(out.cpu().numpy().reshape(-1, 4).astype(np.float64), res,
+                                    G.PARITY_TOL)
+        assert failing == 0, ("vox", v.W, v.H, err)
+    cache.destroy()
+
+
 def test_schedule_argument_checked():
     import paper_2103_10380_amd as fn
     with pytest.raises(ValueError):
         fn.set_schedule("sideways")
     with pytest.raises(fn.FastNeRFError):
-        fn._lib.check(fn.lib().fastnerf_set_schedule(4))
+        fn._lib.check(fn.lib().fastnerf_set_schedule(5))
     assert fn.get_schedule() == "auto"
