@@ -1067,23 +1067,30 @@ def main():
                                      HBM_PEAK_GBS, 4)})
     line["variants"] = variants
     if not args.no_extras and not args.no_single:
-        # the a9 mechanism: the same FP32 launches with one tile per wave
-        fn.set_schedule("tiles")
-        wall_t, step_t, _ = time_batched(fn, caches["f32"], views, N, eps, args.steps,
-                                         args.warmup)
-        frame_t = time_single(fn, caches["f32"], views, N, eps, 2, 1)
+        # the a9 schedules: the same FP32 launches (the 40-view batch, and the
+        # views one launch each) under each schedule
+        per = {}
+        for sch in ("tiles", "wide", "split", "refill"):
+            fn.set_schedule(sch)
+            wall_t, step_t, _ = time_batched(fn, caches["f32"], views, N, eps, args.steps,
+                                             args.warmup)
+            frame_t = time_single(fn, caches["f32"], views, N, eps, 2, 1)
+            per[sch] = {"launch_ms_mean": round(float(np.mean(step_t)), 4),
+                        "single_view_frame_ms_p50": round(float(np.percentile(frame_t, 50)), 4),
+                        "single_view_frame_ms_p99": round(float(np.percentile(frame_t, 99)), 4)}
         fn.set_schedule(args.schedule)
         line["schedule_compare"] = {
-            "note": "FP32 cache; refill = wave-level ray queue (ballot, LDS pool, refill), "
-                    "tiles = one 8x8 tile per wave until its slowest ray stops",
+            "note": ("FP32 cache. tiles = one 8x8 tile per wave until its slowest ray stops "
+                     "(bitgrid in LDS); wide = tiles with more records in flight per lane; "
+                     "split = 4x4 tiles, four lanes per ray (single views; batches run wide); "
+                     "refill = wave-level ray queue (ballot, LDS pool, refill). auto = split "
+                     "(or wide) up to 20,000 8x8 tiles, tiles above"),
             "schedule": args.schedule,
             "default": {
                 "launch_ms_mean": round(float(np.mean(r32["step_ms"])), 4),
                 "single_view_frame_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
                 "single_view_frame_ms_p99": round(float(np.percentile(frame_ms, 99)), 4)},
-            "tiles": {"launch_ms_mean": round(float(np.mean(step_t)), 4),
-                      "single_view_frame_ms_p50": round(float(np.percentile(frame_t, 50)), 4),
-                      "single_view_frame_ms_p99": round(float(np.percentile(frame_t, 99)), 4)}}
+            **per}
         log(f"schedules: {line['schedule_compare']}")
     if not args.no_extras:
         # the served path per storage format on one resident copy of the same
