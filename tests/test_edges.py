@@ -1,0 +1,82 @@
+"""Edge cases of the render path against the FP64 oracle through the C ABI: the
+smallest cache (one voxel, one component, one direction cell), the most
+components (D = 16, the widest kernels), the sample-count bounds (N = 1 and
+N = 4096), the termination bounds (eps = 0, 0.5, 0.999) and long thin images
+(thousands of tiles in one row or column), each under the default schedule and
+one tile per wave (bitwise equal). Where many samples of a ray sit within the
+admissibility band of a voxel face (N = 4096 on a 16^3 grid puts samples 0.007
+voxel apart) or of the stop point (eps near 1), most pixels have more
+ambiguous lookups than the oracle enumerates; those are checked against the
+oracle's interval bounds of all their admissible results instead, so these
+tests allow that share of pixels."""
+import numpy as np
+import pytest
+
+import synth
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(seed, k, D, l, density=0.6):
+    rng = np.random.default_rng(seed)
+    sig = (rng.uniform(2, 40, (k, k, k)) * (rng.uniform(size=(k, k, k)) < density)).astype(
+        np.float32)
+    u = rng.uniform(-1, 1, (k, k, k, D, 3)).astype(np.float32)
+    beta = rng.dirichlet(np.ones(D), (l, l)).astype(np.float32)
+    return sig, u, beta
+
+
+def _check(sig, u, beta, v, N, eps, *, storage="f32", brick=8, in_box=True, bg=(0.3, 0.5, 0.7),
+           max_unchecked=0.01):
+    import torch
+    import paper_2103_10380_amd as fn
+    cache = G.make_cache(sig, u, beta, storage=storage, brick=brick, in_box=in_box, bg=bg)
+    outs = {}
+    try:
+        for sch in ("auto", "tiles"):
+            fn.set_schedule(sch)
+            outs[sch] = fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, N, eps)
+            torch.cuda.synchronize()
+    finally:
+        fn.set_schedule("auto")
+        cache.destroy()
+    assert torch.equal(outs["auto"], outs["tiles"])
+    sc = G.oracle_scene(sig, u, beta, storage=storage, in_box=in_box, bg=bg)
+    res = G.oracle_render(sc, v, N, eps)
+    gpu = outs["auto"].cpu().numpy().reshape(-1, 4).astype(np.float64)
+    err, failing, _ = G.compare(gpu, res, G.PARITY_TOL, max_unchecked=max_unchecked)
+    assert failing == 0, err
+    return gpu
+
+
+def test_one_voxel_one_component_one_cell():
+    sig = np.full((1, 1, 1), 3.0, np.float32)
+    u = np.asarray([0.2, -0.4, 0.9], np.float32).reshape(1, 1, 1, 1, 3)
+    beta = np.ones((1, 1, 1), np.float32)
+    v = synth.orbit_view(3.0, 0.6, 0.3, 24, 20, 0.0, 100.0)
+    for brick in (0, 1):
+        gpu = _check(sig, u, beta, v, 64, 1e-4, brick=brick, max_unchecked=0.05)
+        assert (gpu[:, 3] > 0).any()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "fp8"])
+def test_sixteen_components(storage):
+    sig, u, beta = _scene(3, 16, 16, 9)
+    v = synth.orbit_view(3.1, 2.2, -0.4, 40, 33, 0.0, 100.0)
+    _check(sig, u, beta, v, 96, 1e-3, storage=storage, brick=4)
+
+
+@pytest.mark.parametrize("N,eps", [(1, 0.0), (1, 0.5), (4096, 0.0), (4096, 1e-4), (300, 0.999),
+                                   (300, 0.5)])
+def test_sample_count_and_termination_bounds(N, eps):
+    sig, u, beta = _scene(4, 16, 4, 8)
+    v = synth.orbit_view(2.8, 0.3, 0.7, 24, 24, 0.0, 100.0)
+    _check(sig, u, beta, v, N, eps, max_unchecked=1.0 if N > 1000 else 0.1)
+
+
+@pytest.mark.parametrize("W,H", [(4100, 1), (1, 4100), (8192, 2)])
+def test_long_thin_images(W, H):
+    sig, u, beta = _scene(5, 16, 4, 8)
+    v = synth.orbit_view(3.0, 0.8, 0.2, W, H, 0.0, 100.0, f=900.0)
+    _check(sig, u, beta, v, 48, 1e-3)
