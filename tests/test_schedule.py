@@ -99,8 +99,9 @@ def test_refill_paper_like_scene_and_no_grid():
         c.destroy()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "fp8"])
-def test_split_single_views_of_any_size(storage):
+@pytest.mark.parametrize("storage,sparse", [("f32", False), ("f16", False), ("fp8", False),
+                                            ("f32", True), ("fp8", True)])
+def test_split_single_views_of_any_size(storage, sparse):
     """Split rays (4x4 tiles, four lanes per ray) on single views whose sides
     are not multiples of 4 (partial tiles at the right and bottom edges), in
     the box and between near and far: bitwise the tile schedule's image, and
@@ -109,7 +110,7 @@ def test_split_single_views_of_any_size(storage):
     import paper_2103_10380_amd as fn
     sig, u, beta = G.config1_scene()
     for in_box in (False, True):
-        cache = G.make_cache(sig, u, beta, storage=storage, in_box=in_box)
+        cache = G.make_cache(sig, u, beta, storage=storage, in_box=in_box, sparse=sparse)
         sc = G.oracle_scene(sig, u, beta, storage=storage, in_box=in_box)
         for (W, H) in [(37, 29), (1, 3), (8, 8), (13, 66)]:
             v = synth.orbit_view(3.2, 0.9, 0.3, W, H, 0.0 if in_box else 2.0,
