@@ -102,6 +102,7 @@ struct RenderArgs {
   const int *dyn_total;     // serving: {tile count, view count} of the step (device)
   int vox;                  // 1: voxel traversal (every view has N = 0)
   long long fill_px;        // pixels outside the views' render rectangles (host: grid size)
+  int interleave;           // > 0: views of equal tile counts interleaved in groups of this many
   int sched;                // kSchedTiles, kSchedRefill or kSchedWide
 };
 

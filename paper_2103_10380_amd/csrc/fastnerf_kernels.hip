@@ -741,6 +741,29 @@ __device__ __forceinline__ int view_of_tile(const RenderArgs &a, int tile, int n
   return lo;
 }
 
+// View of launch tile `tile` in a batch, and its tile lt within that view:
+// views one after another (tile_begin ascending), or, when every view of the
+// batch has the same tiles, groups of `interleave` consecutive views one after
+// another with the tiles of a group's views interleaved (tile r of a group of
+// n views: view r % n, its tile r / n), so that the launch works through the
+// same part of the group's views at once and its end holds their last rows
+// rather than one view's heaviest tiles.
+__device__ __forceinline__ int batch_tile(const RenderArgs &a, int tile, int &lt) {
+  if (a.interleave > 0) {
+    const int tpv = a.total_tiles / a.nviews;
+    const int span = a.interleave * tpv;
+    const int grp = tile / span;
+    const int g0 = grp * a.interleave;
+    const int n = min(a.interleave, a.nviews - g0);
+    const int r = tile - grp * span;
+    lt = r / n;
+    return g0 + (r - lt * n);
+  }
+  const int v = view_of_tile(a, tile, a.nviews);
+  lt = tile - a.views[v].tile_begin + a.views[v].tile_offset;
+  return v;
+}
+
 // One cache, one storage format: single views (inline descriptor) or a batch
 // of views in one launch. Each wave renders one 8x8 tile at a time, one ray
 // per lane, taking tiles from its queue until the queue is empty.
@@ -755,9 +778,9 @@ __device__ __forceinline__ void render_queue(const RenderArgs &a,
     const int tile = queue_fetch(Q, lane);
     if (tile < 0) break;
     if (a.views) {
-      const DevView V = a.views[view_of_tile(a, tile, a.nviews)];
-      render_tile<FMT, MAXD, LIN, SPARSE, B, OL>(a, a.c, V, tile - V.tile_begin + V.tile_offset,
-                                                 lane, locc);
+      int lt;
+      const DevView V = a.views[batch_tile(a, tile, lt)];
+      render_tile<FMT, MAXD, LIN, SPARSE, B, OL>(a, a.c, V, lt, lane, locc);
     } else {
       render_tile<FMT, MAXD, LIN, SPARSE, B, OL>(a, a.c, a.v0, tile, lane, locc);
     }
@@ -1041,8 +1064,8 @@ __device__ __forceinline__ void render_refill(const RenderArgs &a) {
             qdone = true;
             break;
           }
-          const DevView V = a.views ? a.views[view_of_tile(a, tile, a.nviews)] : a.v0;
-          const int lt = a.views ? tile - V.tile_begin + V.tile_offset : tile;
+          int lt = tile;
+          const DevView V = a.views ? a.views[batch_tile(a, tile, lt)] : a.v0;
           int px, py;
           tile_pixel<8>(V, lt, lane & 7, lane >> 3, px, py);
           bool march = false;
@@ -1193,8 +1216,9 @@ __global__ void __launch_bounds__(kBlock) k_render_vox(RenderArgs a) {
     const int tile = queue_fetch(Q, lane);
     if (tile < 0) break;
     if (a.views) {
-      const DevView V = a.views[view_of_tile(a, tile, a.nviews)];
-      render_tile_vox<FMT, MAXD>(a, a.c, V, tile - V.tile_begin + V.tile_offset, lane);
+      int lt;
+      const DevView V = a.views[batch_tile(a, tile, lt)];
+      render_tile_vox<FMT, MAXD>(a, a.c, V, lt, lane);
     } else {
       render_tile_vox<FMT, MAXD>(a, a.c, a.v0, tile, lane);
     }

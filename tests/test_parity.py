@@ -163,12 +163,16 @@ def test_render_batch_equals_single_renders():
     cache = G.make_cache(sig, u, beta, storage="f16", pos_linear=True, in_box=True)
     views = synth.random_views(6, 2, [(64, 64), (40, 24), (33, 17)], (3.0, 5.0), (-1.0, 1.0),
                                0.0, 10.0)
-    outs = fn.render_batch(cache, views, 96, 1e-4)
-    torch.cuda.synchronize()
-    for v, o in zip(views, outs):
-        single = fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, 96, 1e-4)
+    # uneven sizes (views one after another) and one size (tiles of the views
+    # interleaved in the launch)
+    same = synth.random_views(5, 3, [(48, 40)], (3.0, 5.0), (-1.0, 1.0), 0.0, 10.0)
+    for batch in (views, same):
+        outs = fn.render_batch(cache, batch, 96, 1e-4)
         torch.cuda.synchronize()
-        assert torch.equal(o, single)
+        for v, o in zip(batch, outs):
+            single = fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, 96, 1e-4)
+            torch.cuda.synchronize()
+            assert torch.equal(o, single)
 
 
 def test_concurrent_streams_equal_serial_renders():
