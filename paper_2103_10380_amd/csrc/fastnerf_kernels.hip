@@ -219,9 +219,21 @@ __device__ __forceinline__ void fill_outside(const RenderArgs &a) {
     if (x0 == 0 && y0 == 0 && x1 >= W && y1 >= H) continue;
     float4 *out = reinterpret_cast<float4 *>(V->out);
     const long long n = (long long)W * H;
+    if (gt >= n) continue;
+    // (x, y) of pixel p, stepped by nt pixels without a division per step
+    const long long sy = nt / W;
+    const int sx = (int)(nt - sy * W);
+    long long yy = gt / W;
+    int x = (int)(gt - yy * W);
     for (long long p = gt; p < n; p += nt) {
-      const int y = (int)(p / W), x = (int)(p - (long long)y * W);
+      const int y = (int)yy;
       if (x < x0 || x >= x1 || y < y0 || y >= y1) out[p] = bgp;
+      x += sx;
+      yy += sy;
+      if (x >= W) {
+        x -= W;
+        ++yy;
+      }
     }
   }
 }

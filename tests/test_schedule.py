@@ -149,10 +149,11 @@ def _rect_views():
 
 @pytest.mark.parametrize("in_box", [False, True])
 def test_render_rectangle_cases(in_box):
-    """Pixels outside a view's render rectangle are written as background by
-    the kernel's fill pass, the others by the tiles; single views (every
-    schedule), a batch of them and the voxel traversal all match the oracle,
-    and the batch equals the single renders bitwise."""
+    """Pixels outside a single view's render rectangle are written as
+    background by the kernel's fill pass, the others by the tiles; single views
+    (every schedule) and the voxel traversal match the oracle, and a batch of
+    the same views (which covers whole images) equals the single renders
+    bitwise."""
     import torch
     import paper_2103_10380_amd as fn
     sig, u, beta = G.config1_scene()
