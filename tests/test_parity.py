@@ -175,6 +175,32 @@ def test_render_batch_equals_single_renders():
             assert torch.equal(o, single)
 
 
+@pytest.mark.parametrize("n", [11, 16])
+def test_interleaved_batches_equal_single_renders(n):
+    """Batches of one view size deal their tiles in groups of 8 interleaved
+    views: 11 views (a group of 8 and one of 3) and 16 (two groups), under the
+    tile and refill schedules and with N = 0, equal the single renders
+    bitwise."""
+    import torch
+    import paper_2103_10380_amd as fn
+    sig, u, beta = G.config1_scene()
+    cache = G.make_cache(sig, u, beta, in_box=True)
+    views = synth.random_views(n, 9, [(40, 24)], (2.5, 5.0), (-1.0, 1.0), 0.0, 10.0)
+    try:
+        for sch in ("tiles", "refill"):
+            fn.set_schedule(sch)
+            for N in (64, 0):
+                outs = fn.render_batch(cache, views, N, 1e-4)
+                torch.cuda.synchronize()
+                for v, o in zip(views, outs):
+                    single = fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, N, 1e-4)
+                    torch.cuda.synchronize()
+                    assert torch.equal(o, single), (sch, N)
+    finally:
+        fn.set_schedule("auto")
+        cache.destroy()
+
+
 def test_concurrent_streams_equal_serial_renders():
     """One cache rendered from two streams at once (each stream has its own
     tile counters and descriptor staging): every image equals the one
