@@ -711,7 +711,10 @@ def line_ceiling(gib=32, regions_kib=(64, 2048, 65536), blocks=16384, iters=32, 
     each wave reads random lines inside a random region per round, lanes reading
     whole lines, 32-byte pieces, or one line per 8 lanes. The render's record
     gathers reach HBM as such lines, so this is the achievable rate they are
-    measured against (the HBM peak assumes streaming)."""
+    measured against (the HBM peak assumes streaming). A buffer of a few MiB
+    stays in the L2 and one of some hundred MiB in the memory-side cache, so
+    small sizes give the rates of those levels; regions larger than the buffer
+    are skipped."""
     import ctypes
     import torch
     lb = ctypes.CDLL(os.path.join(ROOT, "paper_2103_10380_amd", "liblinebench.so"))
@@ -719,7 +722,9 @@ def line_ceiling(gib=32, regions_kib=(64, 2048, 65536), blocks=16384, iters=32, 
     fnl.restype = ctypes.c_int
     fnl.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                     ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
-    nbytes = gib << 30
+    nbytes = int(gib * (1 << 30)) // 128 * 128
+    if nbytes < 128:
+        raise ValueError("line buffer below one line")
     buf = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
     sink = torch.zeros(4, dtype=torch.float32, device="cuda")
     st = torch.cuda.current_stream()
@@ -729,6 +734,9 @@ def line_ceiling(gib=32, regions_kib=(64, 2048, 65536), blocks=16384, iters=32, 
         if mode not in modes:
             continue
         for rk in regions_kib:
+            if (rk << 10) > nbytes:
+                continue
+
             def go(seed):
                 rc = fnl(buf.data_ptr(), nbytes, rk << 10, mode, blocks, iters, seed,
                          sink.data_ptr(), st.cuda_stream)
@@ -827,7 +835,8 @@ def main():
                     help="--line-ceiling: region sizes in KiB, comma-separated")
     ap.add_argument("--line-modes", default="0,1,2",
                     help="--line-ceiling: 0 line per lane, 1 32 B per lane, 2 line per 8 lanes")
-    ap.add_argument("--line-gib", type=int, default=32, help="--line-ceiling: buffer size")
+    ap.add_argument("--line-gib", type=float, default=32,
+                    help="--line-ceiling: buffer size in GiB (fractions allowed, e.g. 0.002 for 2 MiB)")
     ap.add_argument("--pmc-kernel", default="k_render_locc<0, 8, false>",
                     help="kernel name (substring) that --pmc-traffic reports")
     args = ap.parse_args()

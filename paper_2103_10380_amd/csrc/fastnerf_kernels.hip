@@ -809,6 +809,11 @@ constexpr int kSplitJumps = FNR_SPLIT_JUMPS;
 #ifndef FNR_SPLIT_WAVES
 #define FNR_SPLIT_WAVES 0
 #endif
+#ifndef FNR_SPLIT_WIN
+#define FNR_SPLIT_WIN FNR_WIN
+#endif
+constexpr int kSplitWin = FNR_SPLIT_WIN;  // samples per window of a split ray
+static_assert(kSplitWin % 4 == 0 && kSplitWin <= 32, "split windows: 4 to 32 samples");
 
 // Quad (four-lane group) exchanges through DPP: the value of lane Q of each
 // quad to every lane of the quad, and the OR over a quad. Every lane of a
@@ -828,12 +833,13 @@ __device__ __forceinline__ uint32_t quad_or(uint32_t v) {
 }
 
 // One window of a ray held by a quad (lane sub = 0..3 of the quad): the scan
-// of the window's kWin samples is shared (lane sub tests samples sub, sub + 4,
+// of the window's kSplitWin samples is shared (lane sub tests samples sub, sub + 4,
 // ...; the quad ORs the bits; lane 3 reads the last sample's brick distance),
 // and each gather round fetches the window's next four occupied samples, one
-// per lane, one record each. Every lane then composites the round's samples
-// in order with the same operations as ray_window, so the ray state stays the
-// same in all four lanes and the image equals the tile schedule's bitwise.
+// per lane, one record each. Every lane then steps the ray through the
+// round's samples in order, each lane computing the weight of its own sample,
+// with the same operations as ray_window, so the ray state stays the same in
+// all four lanes and the image equals the tile schedule's bitwise.
 template <int FMT, int MAXD>
 __device__ __forceinline__ void split_window(const DevCache &c, Ray<FMT, MAXD> &r, bool &alive,
                                              float s0, int sub) {
@@ -846,10 +852,10 @@ __device__ __forceinline__ void split_window(const DevCache &c, Ray<FMT, MAXD> &
   const float fi = (float)r.i;
   uint32_t part = 0u, dl = 0u;
   if (alive) {
-    uint32_t word[kWin / 4], bitpos[kWin / 4];
-    bool in[kWin / 4];
+    uint32_t word[kSplitWin / 4], bitpos[kSplitWin / 4];
+    bool in[kSplitWin / 4];
 #pragma unroll
-    for (int q = 0; q < kWin / 4; ++q) {
+    for (int q = 0; q < kSplitWin / 4; ++q) {
       const int j = sub + 4 * q;
       const float t = (fi + ((float)j + 0.5f)) * dt;
       const float gx = fmaf(t, r.gd[0], r.og[0]), gy = fmaf(t, r.gd[1], r.og[1]),
@@ -861,17 +867,17 @@ __device__ __forceinline__ void split_window(const DevCache &c, Ray<FMT, MAXD> &
                                  (uint32_t)z >> c.oshift, (uint32_t)c.nbo);
       word[q] = __ldg(c.occ + (bit >> 5));
       bitpos[q] = bit & 31u;
-      if (q == kWin / 4 - 1 && sub == 3)
+      if (q == kSplitWin / 4 - 1 && sub == 3)
         dl = __ldg(c.dist + grid3((uint32_t)x >> c.dshift, (uint32_t)y >> c.dshift,
                                   (uint32_t)z >> c.dshift, (uint32_t)c.nbd));
     }
 #pragma unroll
-    for (int q = 0; q < kWin / 4; ++q)
+    for (int q = 0; q < kSplitWin / 4; ++q)
       part |= (uint32_t)(in[q] && ((word[q] >> bitpos[q]) & 1u)) << (sub + 4 * q);
   }
   uint32_t mask = quad_or(part);
   const uint32_t dlast = quad_from<3>(dl);
-  int next = r.i + kWin;
+  int next = r.i + kSplitWin;
   if (dlast >= 2u) {
     const float run = fminf(((float)(dlast - 1u) * bedge - 0.5f) * r.inv_step, (float)N);
     next += (int)run;
@@ -902,11 +908,39 @@ __device__ __forceinline__ void split_window(const DevCache &c, Ray<FMT, MAXD> &
       rec_colour<FMT, MAXD>(w, r.cw, cr, cg, cb);
       sd = sg * dt;
     }
-    const uint32_t hv = have ? 1u : 0u;
-    const uint32_t h[4] = {quad_from<0>(hv), quad_from<1>(hv), quad_from<2>(hv),
-                           quad_from<3>(hv)};
-    const float sdq[4] = {quad_from<0>(sd), quad_from<1>(sd), quad_from<2>(sd),
-                          quad_from<3>(sd)};
+    // The round's transmittance steps first: every lane of the quad runs the
+    // same optical-depth prefix over the four samples (a lane without a
+    // sample sends -1), then each lane weighs only its own sample and the
+    // weights and colours are gathered into the running sums in order. Each
+    // value is the same expression as in ray_window, so the pixel is too.
+    const float sdh = have ? sd : -1.0f;
+    const float sdq[4] = {quad_from<0>(sdh), quad_from<1>(sdh), quad_from<2>(sdh),
+                          quad_from<3>(sdh)};
+    bool uq[4];
+    float tq[4];
+    {
+#pragma clang fp contract(off)
+      float tau = r.tau;
+      bool al = alive;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uq[q] = !(sdq[q] < 0.0f) && al;
+        tq[q] = tau;
+        tau = tau + (uq[q] ? sdq[q] : 0.0f);
+        al = al && !(tau > r.lim);
+      }
+      r.tau = tau;
+      alive = al;
+    }
+    float wown;
+    {
+#pragma clang fp contract(off)
+      const bool use = sub == 0 ? uq[0] : sub == 1 ? uq[1] : sub == 2 ? uq[2] : uq[3];
+      const float t0 = sub == 0 ? tq[0] : sub == 1 ? tq[1] : sub == 2 ? tq[2] : tq[3];
+      wown = exp_neg(t0) * opacity(use ? sd : 0.0f);
+    }
+    const float wq[4] = {quad_from<0>(wown), quad_from<1>(wown), quad_from<2>(wown),
+                         quad_from<3>(wown)};
     const float crq[4] = {quad_from<0>(cr), quad_from<1>(cr), quad_from<2>(cr),
                           quad_from<3>(cr)};
     const float cgq[4] = {quad_from<0>(cg), quad_from<1>(cg), quad_from<2>(cg),
@@ -916,14 +950,9 @@ __device__ __forceinline__ void split_window(const DevCache &c, Ray<FMT, MAXD> &
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma clang fp contract(off)
-      const bool use = h[q] != 0u && alive;
-      const float sdu = use ? sdq[q] : 0.0f;
-      const float wgt = exp_neg(r.tau) * opacity(sdu);
-      r.cr = fmaf(wgt, use ? crq[q] : 0.0f, r.cr);
-      r.cg = fmaf(wgt, use ? cgq[q] : 0.0f, r.cg);
-      r.cb = fmaf(wgt, use ? cbq[q] : 0.0f, r.cb);
-      r.tau = r.tau + sdu;
-      alive = alive && !(r.tau > r.lim);
+      r.cr = fmaf(wq[q], uq[q] ? crq[q] : 0.0f, r.cr);
+      r.cg = fmaf(wq[q], uq[q] ? cgq[q] : 0.0f, r.cg);
+      r.cb = fmaf(wq[q], uq[q] ? cbq[q] : 0.0f, r.cb);
     }
   }
   if (alive) {
@@ -967,10 +996,11 @@ __device__ __forceinline__ void render_tile_split(const DevCache &c, const DevVi
 }
 
 // Single views with split rays: each wave takes 4x4 tiles from its queue.
-// E4M3 is compiled for 4 waves per SIMD (single views 4% faster than at the
-// 3 its registers would give); the others are left to the compiler.
+// FP32 and E4M3 are compiled for 4 waves per SIMD (single views 4-5% faster
+// than at the 3 their registers would give); FP16 and BF16 reach 4 without
+// the hint and were measured slower with it.
 constexpr int split_waves(int fmt) {
-  return FNR_SPLIT_WAVES > 0 ? FNR_SPLIT_WAVES : (fmt == 3 ? 4 : 1);
+  return FNR_SPLIT_WAVES > 0 ? FNR_SPLIT_WAVES : (fmt == 0 || fmt == 3 ? 4 : 1);
 }
 template <int FMT, int MAXD>
 __global__ void __launch_bounds__(kBlock)
