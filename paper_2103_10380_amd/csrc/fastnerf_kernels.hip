@@ -37,6 +37,10 @@ namespace fnr {
 #define FNR_BATCH_F8 4
 #endif
 constexpr int kWin = FNR_WIN;
+// Wave priority raised while a gather round issues its record loads (0: off).
+#ifndef FNR_PRIO
+#define FNR_PRIO 1
+#endif
 
 template <int FMT, bool LIN> struct Batch {
   static constexpr int value =
@@ -369,9 +373,14 @@ __device__ __forceinline__ void ray_window(const DevCache &c, Ray<FMT, MAXD> &r,
       for (int b = 0; b < B; ++b)
         off[b] = SPARSE ? record_offset_in(c, sb[b], vx[b], vy[b], vz[b])
                         : record_offset(c, vx[b], vy[b], vz[b]);
+      // the loads go out at a raised wave priority, so that a wave about to
+      // wait on memory issues them ahead of waves busy with scans or
+      // composites on the same SIMD (measured: FP32 launches 1.5-2% faster)
+      if (FNR_PRIO) __builtin_amdgcn_s_setprio(2);
 #pragma unroll
       for (int b = 0; b < B; ++b)
         if (have[b] && alive) load_record<FMT, MAXD>(c, off[b], w[b]);
+      if (FNR_PRIO) __builtin_amdgcn_s_setprio(0);
       // all B records are requested before the first is used, each only
       // by the lanes that have a sample in its slot (the others issue no
       // memory request); an unused slot (past the window's last occupied
