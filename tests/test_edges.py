@@ -80,3 +80,33 @@ def test_long_thin_images(W, H):
     sig, u, beta = _scene(5, 16, 4, 8)
     v = synth.orbit_view(3.0, 0.8, 0.2, W, H, 0.0, 100.0, f=900.0)
     _check(sig, u, beta, v, 48, 1e-3)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "fp8"])
+@pytest.mark.parametrize("D", [3, 6])
+def test_split_rays_every_format_and_width(storage, D):
+    """Split rays (the default for a small single view) for each storage format
+    at both component classes they are built for (D <= 4 and D <= 8), with the
+    ray stopping inside a gather round (eps = 0.05 on a dense random grid):
+    bitwise the tile schedule's image, and the oracle's."""
+    import torch
+    import paper_2103_10380_amd as fn
+    sig, u, beta = _scene(7 + D, 24, D, 11, density=0.35)
+    v = synth.orbit_view(2.9, 1.3, 0.5, 29, 35, 0.0, 100.0)
+    cache = G.make_cache(sig, u, beta, storage=storage, brick=4, in_box=True, bg=(0.2, 0.6, 0.4))
+    outs = {}
+    try:
+        for sch in ("split", "tiles"):
+            fn.set_schedule(sch)
+            outs[sch] = fn.render(cache, v.K, v.c2w, v.H, v.W, v.near, v.far, 160, 0.05)
+            torch.cuda.synchronize()
+    finally:
+        fn.set_schedule("auto")
+        cache.destroy()
+    assert torch.equal(outs["split"], outs["tiles"]), (storage, D)
+    sc = G.oracle_scene(sig, u, beta, storage=storage, in_box=True, bg=(0.2, 0.6, 0.4))
+    res = G.oracle_render(sc, v, 160, 0.05)
+    gpu = outs["split"].cpu().numpy().reshape(-1, 4).astype(np.float64)
+    err, failing, _ = G.compare(gpu, res, G.PARITY_TOL, max_unchecked=0.1)
+    assert failing == 0, (storage, D, err)
+    assert (gpu[:, 3] > 0.5).mean() > 0.2, "few rays reach the stop point"
