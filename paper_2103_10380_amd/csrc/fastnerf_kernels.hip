@@ -1156,10 +1156,27 @@ __device__ __forceinline__ void render_refill(const RenderArgs &a) {
   queue_retire(Q, lane);
 }
 
-// Waves per SIMD of the LDS-staged tile kernel: those of k_render.
+// Waves per SIMD of the LDS-staged tile kernel and its records in flight per
+// lane: FP32 holds two records at 3 waves per SIMD (with the loads issued at
+// raised priority, 3-4% faster than one record at 4 waves); the others as
+// k_render.
 #ifndef FNR_LDS_WAVES_F32
-#define FNR_LDS_WAVES_F32 4
+#define FNR_LDS_WAVES_F32 3
 #endif
+#ifndef FNR_LOCC_BATCH_F32
+#define FNR_LOCC_BATCH_F32 2
+#endif
+#ifndef FNR_LOCC_BATCH_F16
+#define FNR_LOCC_BATCH_F16 FNR_BATCH_F16
+#endif
+#ifndef FNR_LOCC_BATCH_F8
+#define FNR_LOCC_BATCH_F8 FNR_BATCH_F8
+#endif
+template <int FMT, bool LIN> struct LoccBatch {
+  static constexpr int value =
+      LIN ? Batch<FMT, LIN>::value
+          : (FMT == 0 ? FNR_LOCC_BATCH_F32 : (FMT == 3 ? FNR_LOCC_BATCH_F8 : FNR_LOCC_BATCH_F16));
+};
 #ifndef FNR_LDS_WAVES_F16
 #define FNR_LDS_WAVES_F16 4
 #endif
@@ -1220,7 +1237,7 @@ __global__ void __launch_bounds__(kWave * 4 * lds_waves(FMT))
       if (i0 + q * nt < n4) locc4[i0 + q * nt] = v[q];
   }
   __syncthreads();
-  render_queue<FMT, MAXD, LIN, false, Batch<FMT, LIN>::value, true>(
+  render_queue<FMT, MAXD, LIN, false, LoccBatch<FMT, LIN>::value, true>(
       a, reinterpret_cast<const uint32_t *>(locc4));
 }
 
